@@ -1,0 +1,78 @@
+"""The pins must catch plausible mistakes.  Each mutant below is the oracle's
+union-find with one planted error (run on the CPU only); the pins used against
+the real oracle -- hand-worked cases, breadth-first brute force and the
+labeling invariants -- must reject every mutant."""
+import numpy as np
+import pytest
+
+import oracle
+from test_oracle import check_invariants, load_cases
+
+
+def _uf_label(n, src, dst, occ, *, link_larger=False, ignore_occ=False, no_final=False,
+              skip_reversed=False, drop_last=False, same_endpoint=False):
+    parent = list(range(n))
+
+    def root(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+
+    m = len(src) - (1 if drop_last and len(src) else 0)
+    for b in range(m):
+        if not ignore_occ and not occ[b]:
+            continue
+        u, v = int(src[b]), int(dst[b])
+        if same_endpoint:
+            v = u
+        if skip_reversed and u > v:
+            continue
+        ru, rv = root(u), root(v)
+        if ru == rv:
+            continue
+        lo, hi = min(ru, rv), max(ru, rv)
+        if link_larger:
+            parent[lo] = hi
+        else:
+            parent[hi] = lo
+    if no_final:
+        return np.array(parent, np.int32)
+    return np.array([root(i) for i in range(n)], np.int32)
+
+
+MUTANTS = {
+    "links the smaller root under the larger": dict(link_larger=True),
+    "ignores the occupancy mask": dict(ignore_occ=True),
+    "skips the final flatten": dict(no_final=True),
+    "drops bonds listed high-to-low": dict(skip_reversed=True),
+    "drops the last bond": dict(drop_last=True),
+    "uses one endpoint twice": dict(same_endpoint=True),
+}
+
+
+def _pins_reject(fn) -> bool:
+    for case in load_cases():
+        n, b = case["n"], case["bonds"]
+        src = np.array([x[0] for x in b], np.int32)
+        dst = np.array([x[1] for x in b], np.int32)
+        occ = np.array([x[2] for x in b], np.uint8)
+        got = fn(n, src, dst, occ)
+        if got.tolist() != case["expect"]:
+            return True
+        if got.tolist() != oracle.label_bfs(n, [(u, v) for u, v, o in b if o]):
+            return True
+        try:
+            check_invariants(got, n, src, dst, occ)
+        except AssertionError:
+            return True
+    return False
+
+
+def test_unmutated_copy_passes_the_pins():
+    assert not _pins_reject(lambda n, s, d, o: _uf_label(n, s, d, o))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name):
+    kw = MUTANTS[name]
+    assert _pins_reject(lambda n, s, d, o: _uf_label(n, s, d, o, **kw)), name
