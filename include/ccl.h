@@ -1,0 +1,222 @@
+/*
+ * ccl.h -- connected-component labeling of occupied bonds on one AMD
+ * Instinct MI355X (gfx950).  C ABI of libccl.so.
+ *
+ * Method: the generalized non-iterative labeling of Komura, "A generalized
+ * GPU-based connected component labeling algorithm" (arXiv:1603.08357):
+ *   (i)   every site starts as its own root, label[i] = i (section 3, step i,
+ *         the case of an empty residual list);
+ *   (iii) every occupied bond joins the roots of its two ends with the
+ *         atomicMin label reduction of Algorithm 1 -- one pass, no
+ *         convergence loop;
+ *   (iv)  the analysis step follows every label to its root (section 3).
+ * On return every site holds the minimum site number of its cluster (section
+ * 3: the label of each cluster is its minimum site number), so the result is
+ * unique and independent of thread scheduling.
+ *
+ * Conventions for every entry point
+ *   - Site ids are 0-based int32; n_sites <= INT32_MAX.
+ *   - "device" pointers are HIP device allocations owned by the caller;
+ *     inputs are read, never written; labels_out is fully overwritten and is
+ *     also the union-find work array, so it must not overlap any input.
+ *   - occupied: one byte per bond, nonzero = occupied (section 4: each bond is
+ *     occupied with probability p); NULL means every bond is occupied.
+ *   - Self-loops change nothing; repeated bonds and both orientations of a
+ *     bond are allowed.
+ *   - stream: a hipStream_t (NULL = the default stream).  Calls only enqueue
+ *     work and return; the caller synchronizes.  No call on this path
+ *     allocates device memory.  Calls on different streams may overlap when
+ *     they touch disjoint buffers.
+ *   - Argument errors are detected on the host before any HIP call and return
+ *     CCL_ERR_INVALID_VALUE.  A site id outside [0, n_sites) on the labeling
+ *     path is undefined behaviour (the kernels do not check ids); use
+ *     ccl_validate_edges / ccl_validate_csr first on untrusted input.
+ *   - After any error the contents of labels_out are unspecified.
+ */
+#ifndef CCL_H
+#define CCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CCL_OK = 0,
+  CCL_ERR_INVALID_VALUE = 1,      /* bad size, NULL pointer, aliasing, bad plan */
+  CCL_ERR_INDEX_OUT_OF_RANGE = 2, /* reported by the validation calls only */
+  CCL_ERR_OUT_OF_MEMORY = 3,      /* plan creation could not allocate */
+  CCL_ERR_HIP = 4,                /* a HIP call failed; see ccl_last_hip_error() */
+  CCL_ERR_NOT_SUPPORTED = 5       /* device is not gfx950 */
+} ccl_status;
+
+/* ---------------------------------------------------------------- labeling */
+
+/*
+ * Label the clusters of an edge list.
+ *   n_sites    number of sites N (0 <= N <= INT32_MAX)
+ *   n_bonds    number of bonds B (>= 0)
+ *   src, dst   device int32[B]: bond b joins src[b] and dst[b]
+ *   occupied   device uint8[B] or NULL
+ *   labels_out device int32[N]: on return, the minimum site id of each site's
+ *              cluster (isolated sites keep their own id)
+ * Kernels: init (step i), bond-parallel merge (step iii, Algorithm 1),
+ * flatten (step iv).
+ */
+ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,
+                     const uint8_t* occupied, int32_t* labels_out, void* stream);
+
+/*
+ * Workspace bytes ccl_label_csr needs for n_sites sites (one bit per site,
+ * rounded up to whole 64-bit words).
+ */
+size_t ccl_label_csr_workspace_size(int64_t n_sites);
+
+/*
+ * Label the clusters of a graph in compressed-sparse-row form: row i holds the
+ * bonds (i, col[e]) for e in [row_ptr[i], row_ptr[i+1]).  Each undirected bond
+ * needs to appear once (a "half" CSR such as forward neighbours only), but
+ * listing it in both rows is also correct.  The paper's neighbour list
+ * (section 3) is this structure with all neighbours listed.
+ *   row_ptr    device int32[N+1], non-decreasing, row_ptr[N] < 2^31
+ *   col        device int32[row_ptr[N]]
+ *   occupied   device uint8[row_ptr[N]] aligned with col, or NULL
+ *   workspace  device buffer of at least ccl_label_csr_workspace_size(N)
+ *              bytes, 8-byte aligned; contents need not be initialised and are
+ *              garbage afterwards.  May be NULL only when N <= 32768 (a single
+ *              tile needs none).
+ * Kernels: sites are cut into tiles of consecutive ids; one workgroup per tile
+ * initialises its labels (step i) and joins the tile-internal bonds in LDS
+ * (step iii on the tile), then the bonds that leave a tile are joined in
+ * global memory (step iii, Algorithm 1) and the labels flattened (step iv).
+ */
+ccl_status ccl_label_csr(int64_t n_sites, const int32_t* row_ptr, const int32_t* col,
+                         const uint8_t* occupied, int32_t* labels_out, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * Many independent instances labelled in one launch.  Instance k owns sites
+ * [site_off[k], site_off[k+1]) and bonds [bond_off[k], bond_off[k+1]) of the
+ * concatenated arrays; src/dst hold instance-LOCAL ids (0 <= id <
+ * site_off[k+1] - site_off[k] <= INT32_MAX) and the labels written are
+ * instance-local.  Offsets are int64 so a batch may exceed 2^31 sites.
+ */
+typedef struct ccl_plan_s* ccl_plan;
+
+/* Tuning of the persistent batched kernel; zero fields take defaults. */
+typedef struct {
+  int32_t block_threads;   /* threads per workgroup (multiple of 64, <= 1024) */
+  int32_t blocks_per_cu;   /* resident workgroups per compute unit */
+  int32_t bonds_per_chunk; /* bonds in one merge work item */
+  int32_t sites_per_chunk; /* sites in one init / flatten work item */
+  int32_t small_sites;     /* instances up to this many sites are labelled
+                              entirely in LDS by one workgroup; 0 = default
+                              (fits the LDS of the resident workgroups),
+                              negative = never */
+} ccl_tuning;
+
+/*
+ * Build a plan for one batch layout: reads the host copies of the offsets,
+ * builds the work-item table and allocates it plus a few counters on the
+ * current device (the only allocation of the batched path).
+ *   n_inst          number of instances K (>= 0)
+ *   site_off_host   host int64[K+1], site_off[0] = 0, non-decreasing
+ *   bond_off_host   host int64[K+1], bond_off[0] = 0, non-decreasing
+ *   tuning          NULL = defaults
+ *   out             receives the plan
+ * Returns CCL_ERR_INVALID_VALUE for bad offsets, CCL_ERR_OUT_OF_MEMORY /
+ * CCL_ERR_HIP when the device allocation fails.
+ */
+ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
+                           const int64_t* bond_off_host, const ccl_tuning* tuning,
+                           ccl_plan* out);
+
+/* Frees a plan (synchronizes the device first). NULL is a no-op. */
+ccl_status ccl_plan_destroy(ccl_plan plan);
+
+/* The tuning a plan resolved to (defaults filled in). */
+ccl_status ccl_plan_get_tuning(ccl_plan plan, ccl_tuning* out);
+
+/*
+ * Synchronous health check after a batched launch has finished: *error_host
+ * is nonzero when a work item gave up waiting for the items it depends on
+ * (its spin limit was hit; the labels of that launch are then unreliable).
+ * The batched kernel bounds every wait, so it always terminates.
+ */
+ccl_status ccl_plan_check(ccl_plan plan, int32_t* error_host);
+
+/*
+ * Label every instance of the plan's layout in one persistent launch (plus a
+ * small kernel that resets the plan's counters; no memset node, so the pair
+ * can be captured into a HIP graph and replayed).
+ *   src, dst   device int32[total bonds], instance-local ids
+ *   occupied   device uint8[total bonds] or NULL
+ *   labels_out device int32[total sites]
+ * A plan may be in flight on one stream at a time.
+ */
+ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* dst,
+                             const uint8_t* occupied, int32_t* labels_out, void* stream);
+
+/*
+ * Reference schedule for batches: one ccl_label call per instance, in order,
+ * on `stream` (the "one launch per instance" baseline).  Host offsets only.
+ */
+ccl_status ccl_label_batched_per_instance(int32_t n_inst, const int64_t* site_off_host,
+                                          const int64_t* bond_off_host, const int32_t* src,
+                                          const int32_t* dst, const uint8_t* occupied,
+                                          int32_t* labels_out, void* stream);
+
+/* ---------------------------------------------------------------- checks */
+
+/*
+ * Count bonds with an end outside [0, n_sites).  Synchronous (waits on
+ * `stream`); off the labeling path.  *n_bad_host receives the count; returns
+ * CCL_ERR_INDEX_OUT_OF_RANGE when it is nonzero.
+ */
+ccl_status ccl_validate_edges(int64_t n_sites, int64_t n_bonds, const int32_t* src,
+                              const int32_t* dst, int64_t* n_bad_host, void* stream);
+
+/*
+ * Count CSR defects: decreasing row_ptr steps, row_ptr[0] < 0, and column ids
+ * outside [0, n_sites).  Synchronous, like ccl_validate_edges.
+ */
+ccl_status ccl_validate_csr(int64_t n_sites, const int32_t* row_ptr, const int32_t* col,
+                            int64_t n_col, int64_t* n_bad_host, void* stream);
+
+/* ---------------------------------------------------------------- utilities */
+
+const char* ccl_status_string(ccl_status s);
+
+/* HIP error code of the last failed HIP call on this host thread (0 = none). */
+int ccl_last_hip_error(void);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int ccl_version(void);
+
+/*
+ * Kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by HIP events recorded on the stream it is launched on.
+ * ccl_trace_enable(1) also clears earlier records.  ccl_trace_count()
+ * synchronizes on the recorded events and returns the number of records;
+ * ccl_trace_get(i, ...) returns the kernel's name (static string) and its
+ * duration in milliseconds.  At most 65536 records are kept.
+ */
+ccl_status ccl_trace_enable(int on);
+int ccl_trace_count(void);
+ccl_status ccl_trace_get(int i, const char** kernel_name, float* ms);
+
+/*
+ * Plain streaming copy of `bytes` bytes (16-byte aligned pointers), used to
+ * calibrate hardware traffic counters against a kernel of known traffic.
+ */
+ccl_status ccl_probe_copy(const void* in, void* out, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCL_H */

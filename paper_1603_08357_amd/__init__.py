@@ -1,0 +1,292 @@
+"""Connected-component labeling of occupied bonds on an AMD MI355X.
+
+Thin ctypes binding of ``libccl.so`` (see ``include/ccl.h``).  Every step of
+the labeling -- init, the Algorithm-1 merge, flatten, the batched persistent
+kernel -- runs in the library's HIP kernels; this module only checks tensor
+devices / dtypes / contiguity and passes raw pointers and the current HIP
+stream.  PyTorch supplies device memory and streams.  There is no CPU fallback:
+if the library is missing or fails to load, importing this package fails.
+"""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import os
+
+import numpy as np
+import torch  # first: the library then binds to the HIP runtime torch loaded
+
+__all__ = [
+    "CclError", "label", "label_csr", "csr_workspace_bytes", "Plan", "Tuning",
+    "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
+    "library_path", "version",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_PKG, "libccl.so")
+
+CCL_OK = 0
+CCL_ERR_INDEX_OUT_OF_RANGE = 2
+
+
+class CclError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.ccl_status_string(status).decode()
+        hip = _lib.ccl_last_hip_error()
+        super().__init__(f"{where}: {msg}" + (f" (hip error {hip})" if status == 4 else ""))
+        self.status = status
+
+
+class Tuning(ctypes.Structure):
+    """ccl_tuning: zero fields take the library defaults."""
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("bonds_per_chunk", ctypes.c_int32), ("sites_per_chunk", ctypes.c_int32),
+                ("small_sites", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError(f"{library_path} is not built; run `python -m paper_1603_08357_amd.build`")
+    lib = ctypes.CDLL(library_path)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "ccl_label": (st, [i64, i64, P, P, P, P, P]),
+        "ccl_label_csr_workspace_size": (sz, [i64]),
+        "ccl_label_csr": (st, [i64, P, P, P, P, P, sz, P]),
+        "ccl_plan_create": (st, [i32, P, P, P, P]),
+        "ccl_plan_destroy": (st, [P]),
+        "ccl_plan_get_tuning": (st, [P, P]),
+        "ccl_plan_check": (st, [P, P]),
+        "ccl_label_batched": (st, [P, P, P, P, P, P]),
+        "ccl_label_batched_per_instance": (st, [i32, P, P, P, P, P, P, P]),
+        "ccl_validate_edges": (st, [i64, i64, P, P, P, P]),
+        "ccl_validate_csr": (st, [i64, P, P, i64, P, P]),
+        "ccl_status_string": (ctypes.c_char_p, [st]),
+        "ccl_last_hip_error": (ctypes.c_int, []),
+        "ccl_version": (ctypes.c_int, []),
+        "ccl_trace_enable": (st, [ctypes.c_int]),
+        "ccl_trace_count": (ctypes.c_int, []),
+        "ccl_trace_get": (st, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                               ctypes.POINTER(ctypes.c_float)]),
+        "ccl_probe_copy": (st, [P, P, sz, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def version() -> int:
+    return _lib.ccl_version()
+
+
+def _check(status: int, where: str):
+    if status != CCL_OK:
+        raise CclError(status, where)
+
+
+def _dev_ptr(t, dtype, name, n=None, device=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _stream(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def label(src: torch.Tensor, dst: torch.Tensor, n_sites: int, occ: torch.Tensor | None = None,
+          out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Min-site-index cluster labels of an edge list (int32 GPU tensors)."""
+    dev = src.device
+    m = src.numel()
+    ps = _dev_ptr(src, torch.int32, "src", None, dev)
+    pd = _dev_ptr(dst, torch.int32, "dst", m, dev)
+    po = _dev_ptr(occ, torch.uint8, "occ", m, dev)
+    if out is None:
+        out = torch.empty(n_sites, dtype=torch.int32, device=dev)
+    pl = _dev_ptr(out, torch.int32, "out", n_sites, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label(n_sites, m, ps, pd, po, pl, _stream(stream, dev)), "ccl_label")
+    return out
+
+
+def csr_workspace_bytes(n_sites: int) -> int:
+    return int(_lib.ccl_label_csr_workspace_size(n_sites))
+
+
+def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None = None,
+              out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1.
+    `workspace` (uint8, >= csr_workspace_bytes(n) bytes) is allocated when None."""
+    dev = row_ptr.device
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must hold n_sites + 1 entries")
+    prp = _dev_ptr(row_ptr, torch.int32, "row_ptr", None, dev)
+    pc = _dev_ptr(col, torch.int32, "col", None, dev)
+    po = _dev_ptr(occ, torch.uint8, "occ", col.numel(), dev)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    pl = _dev_ptr(out, torch.int32, "out", n, dev)
+    need = csr_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=dev)
+    pw = _dev_ptr(workspace, torch.uint8, "workspace", None, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label_csr(n, prp, pc, po, pl, pw, workspace.numel(), _stream(stream, dev)),
+               "ccl_label_csr")
+    return out
+
+
+def _host_i64(a):
+    a = np.ascontiguousarray(np.asarray(a.cpu() if isinstance(a, torch.Tensor) else a),
+                             dtype=np.int64)
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+class Plan:
+    """A batched-labeling plan for one layout of instances (ccl_plan)."""
+
+    def __init__(self, site_off, bond_off, tuning: Tuning | dict | None = None, device=None):
+        so, pso = _host_i64(site_off)
+        bo, pbo = _host_i64(bond_off)
+        if so.shape != bo.shape or so.ndim != 1 or len(so) < 1:
+            raise ValueError("site_off and bond_off must be 1-D with K+1 entries")
+        if isinstance(tuning, dict):
+            tuning = Tuning(**tuning)
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.n_inst = len(so) - 1
+        self.total_sites = int(so[-1])
+        self.total_bonds = int(bo[-1])
+        self._site_off, self._bond_off = so, bo
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ccl_plan_create(self.n_inst, pso, pbo,
+                                        ctypes.byref(tuning) if tuning is not None else None,
+                                        ctypes.byref(self._h)), "ccl_plan_create")
+
+    @property
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(_lib.ccl_plan_get_tuning(self._h, ctypes.byref(t)), "ccl_plan_get_tuning")
+        return t
+
+    def label(self, src, dst, occ=None, out=None, stream=None) -> torch.Tensor:
+        dev = self.device
+        ps = _dev_ptr(src, torch.int32, "src", self.total_bonds, dev)
+        pd = _dev_ptr(dst, torch.int32, "dst", self.total_bonds, dev)
+        po = _dev_ptr(occ, torch.uint8, "occ", self.total_bonds, dev)
+        if out is None:
+            out = torch.empty(self.total_sites, dtype=torch.int32, device=dev)
+        pl = _dev_ptr(out, torch.int32, "out", self.total_sites, dev)
+        with torch.cuda.device(dev):
+            _check(_lib.ccl_label_batched(self._h, ps, pd, po, pl, _stream(stream, dev)),
+                   "ccl_label_batched")
+        return out
+
+    def check(self) -> int:
+        """Nonzero when a work item of the last launch gave up waiting."""
+        v = ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            _check(_lib.ccl_plan_check(self._h, ctypes.byref(v)), "ccl_plan_check")
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                _lib.ccl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def label_batched_per_instance(site_off, bond_off, src, dst, occ=None, out=None, stream=None):
+    """One ccl_label call per instance (the baseline schedule)."""
+    so, pso = _host_i64(site_off)
+    bo, pbo = _host_i64(bond_off)
+    dev = src.device
+    ps = _dev_ptr(src, torch.int32, "src", int(bo[-1]), dev)
+    pd = _dev_ptr(dst, torch.int32, "dst", int(bo[-1]), dev)
+    po = _dev_ptr(occ, torch.uint8, "occ", int(bo[-1]), dev)
+    if out is None:
+        out = torch.empty(int(so[-1]), dtype=torch.int32, device=dev)
+    pl = _dev_ptr(out, torch.int32, "out", int(so[-1]), dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label_batched_per_instance(len(so) - 1, pso, pbo, ps, pd, po, pl,
+                                                   _stream(stream, dev)),
+               "ccl_label_batched_per_instance")
+    return out
+
+
+def validate_edges(src, dst, n_sites: int, stream=None) -> int:
+    """Number of bonds with an end outside [0, n_sites) (synchronous)."""
+    dev = src.device
+    bad = ctypes.c_int64()
+    st = _lib.ccl_validate_edges(n_sites, src.numel(), _dev_ptr(src, torch.int32, "src", None, dev),
+                                 _dev_ptr(dst, torch.int32, "dst", src.numel(), dev),
+                                 ctypes.byref(bad), _stream(stream, dev))
+    if st not in (CCL_OK, CCL_ERR_INDEX_OUT_OF_RANGE):
+        _check(st, "ccl_validate_edges")
+    return bad.value
+
+
+def validate_csr(row_ptr, col, stream=None) -> int:
+    dev = row_ptr.device
+    bad = ctypes.c_int64()
+    st = _lib.ccl_validate_csr(row_ptr.numel() - 1, _dev_ptr(row_ptr, torch.int32, "row_ptr", None, dev),
+                               _dev_ptr(col, torch.int32, "col", None, dev), col.numel(),
+                               ctypes.byref(bad), _stream(stream, dev))
+    if st not in (CCL_OK, CCL_ERR_INDEX_OUT_OF_RANGE):
+        _check(st, "ccl_validate_csr")
+    return bad.value
+
+
+@contextlib.contextmanager
+def trace():
+    """Per-kernel durations of every library launch inside the block:
+    ``with trace() as rec: ...`` then ``rec`` holds (kernel, ms) pairs."""
+    rec = []
+    _check(_lib.ccl_trace_enable(1), "ccl_trace_enable")
+    try:
+        yield rec
+    finally:
+        n = _lib.ccl_trace_count()
+        name, ms = ctypes.c_char_p(), ctypes.c_float()
+        for i in range(max(n, 0)):
+            _check(_lib.ccl_trace_get(i, ctypes.byref(name), ctypes.byref(ms)), "ccl_trace_get")
+            rec.append((name.value.decode(), float(ms.value)))
+        _lib.ccl_trace_enable(0)
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Plain streaming copy (traffic-counter calibration)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    _check(_lib.ccl_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                               nbytes, _stream(stream, src.device)), "ccl_probe_copy")

@@ -1,0 +1,86 @@
+// Host-side internals shared by the translation units of libccl.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ccl.h"
+
+namespace ccl {
+
+struct DeviceInfo {
+  int device = -1;
+  int cu_count = 0;
+  int max_lds_per_block = 0;
+  bool is_gfx950 = false;
+};
+
+// Properties of the current device (queried once per device, then cached).
+// Returns nullptr and records the HIP error when the query fails.
+const DeviceInfo* current_device();
+
+// Record a failed HIP call for ccl_last_hip_error() and map it to a status.
+ccl_status fail_hip(hipError_t e);
+
+// Kernel timing (ccl_trace_*): while enabled, the scope records a HIP event
+// on `stream` when it opens and another when it closes.
+class TraceScope {
+ public:
+  TraceScope(const char* name, hipStream_t stream);
+  ~TraceScope();
+  TraceScope(const TraceScope&) = delete;
+  TraceScope& operator=(const TraceScope&) = delete;
+
+ private:
+  int slot_ = -1;
+  hipStream_t stream_ = nullptr;
+};
+
+// Grid for a grid-stride kernel: enough workgroups to cover `work` items at
+// `per_block` items each, capped at `per_cu` resident workgroups per CU.
+inline unsigned grid_for(int64_t work, int64_t per_block, int per_cu, const DeviceInfo& d) {
+  int64_t need = (work + per_block - 1) / per_block;
+  int64_t cap = (int64_t)d.cu_count * per_cu;
+  if (need < 1) need = 1;
+  return (unsigned)(need < cap ? need : cap);
+}
+
+// True when the byte ranges [a, a+na) and [b, b+nb) intersect.
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Launch + error check; returns from the calling function on failure.
+#define CCL_LAUNCH(name, kernel, grid, block, lds, stream, ...)                          \
+  do {                                                                                  \
+    {                                                                                   \
+      ::ccl::TraceScope ccl_trace_scope_(name, stream);                                 \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, __VA_ARGS__);    \
+    }                                                                                   \
+    hipError_t ccl_launch_err_ = hipGetLastError();                                     \
+    if (ccl_launch_err_ != hipSuccess) return ::ccl::fail_hip(ccl_launch_err_);         \
+  } while (0)
+
+// Launchers (one translation unit each); arguments already validated.
+ccl_status launch_init(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);
+ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);
+ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                              const uint8_t* occ, int32_t* label, hipStream_t s,
+                              const DeviceInfo& d);
+ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                            const uint8_t* occ, int32_t* label, uint64_t* rowmask,
+                            hipStream_t s, const DeviceInfo& d);
+ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                 unsigned long long* d_count, hipStream_t s, const DeviceInfo& d);
+ccl_status launch_validate_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                               int64_t n_col, unsigned long long* d_count, hipStream_t s,
+                               const DeviceInfo& d);
+ccl_status launch_probe_copy(const void* in, void* out, size_t bytes, hipStream_t s,
+                             const DeviceInfo& d);
+
+// Sites per tile of the CSR path (one workgroup, one LDS slot per site).
+constexpr int kCsrTile = 32768;
+
+}  // namespace ccl

@@ -1,0 +1,128 @@
+// Edge-list labeling: init (step i), bond-parallel merge (step iii,
+// Algorithm 1), flatten (step iv).  Paper, section 3.
+#include "common.hpp"
+#include "uf.hpp"
+
+namespace ccl {
+
+constexpr int kBlock = 256;
+
+// Step (i) with every residual list taken as empty: label[i] = i.
+// VEC: label is 16-byte aligned and written four ids at a time.
+template <bool VEC>
+__global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ label, int64_t n) {
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t done = 0;
+  if (VEC) {
+    const int64_t n4 = n >> 2;
+    int4* l4 = reinterpret_cast<int4*>(label);
+    for (int64_t q = tid; q < n4; q += stride) {
+      const int32_t b = (int32_t)(q << 2);
+      l4[q] = make_int4(b, b + 1, b + 2, b + 3);
+    }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + tid; i < n; i += stride) label[i] = (int32_t)i;
+}
+
+// Step (iii), one thread per bond: roots of both ends, then the atomicMin
+// loop of Algorithm 1.  Unoccupied bonds and same-root bonds issue nothing.
+__global__ void __launch_bounds__(kBlock)
+    k_merge_edges(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                  const uint8_t* __restrict__ occ, int64_t m, int32_t* label) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < m; b += stride) {
+    if (occ != nullptr && occ[b] == 0) continue;
+    unite(label, src[b], dst[b]);
+  }
+}
+
+// Step (iv): every site follows its label to the root and stores it.  Other
+// threads may read label[i] meanwhile; they see either the old link or the
+// root, both valid.
+__global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const int32_t p = lab_ld(label + i);
+    if (p == (int32_t)i) continue;
+    const int32_t g = lab_ld(label + p);
+    if (g == p) continue;
+    lab_st(label + i, find_root(label, g));
+  }
+}
+
+ccl_status launch_init(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d) {
+  if (n == 0) return CCL_OK;
+  const bool vec = (reinterpret_cast<uintptr_t>(label) & 15) == 0;
+  const unsigned g = grid_for(vec ? (n + 3) / 4 : n, kBlock, 8, d);
+  if (vec)
+    CCL_LAUNCH("ccl_init", k_init<true>, g, kBlock, 0, s, label, n);
+  else
+    CCL_LAUNCH("ccl_init", k_init<false>, g, kBlock, 0, s, label, n);
+  return CCL_OK;
+}
+
+ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d) {
+  if (n == 0) return CCL_OK;
+  CCL_LAUNCH("ccl_flatten", k_flatten, grid_for(n, kBlock, 8, d), kBlock, 0, s, label, n);
+  return CCL_OK;
+}
+
+ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                              const uint8_t* occ, int32_t* label, hipStream_t s,
+                              const DeviceInfo& d) {
+  ccl_status st = launch_init(n, label, s, d);
+  if (st != CCL_OK) return st;
+  if (m > 0)
+    CCL_LAUNCH("ccl_merge_edges", k_merge_edges, grid_for(m, kBlock, 8, d), kBlock, 0, s, src,
+               dst, occ, m, label);
+  return launch_flatten(n, label, s, d);
+}
+
+// ---------------------------------------------------------------- checks
+
+__global__ void __launch_bounds__(kBlock)
+    k_validate_edges(int64_t n, int64_t m, const int32_t* __restrict__ src,
+                     const int32_t* __restrict__ dst, unsigned long long* count) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  unsigned long long bad = 0;
+  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < m; b += stride) {
+    const int64_t u = src[b], v = dst[b];
+    bad += (u < 0 || u >= n || v < 0 || v >= n) ? 1ull : 0ull;
+  }
+  if (bad) atomicAdd(count, bad);
+}
+
+ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                 unsigned long long* d_count, hipStream_t s, const DeviceInfo& d) {
+  if (m == 0) return CCL_OK;
+  CCL_LAUNCH("ccl_validate_edges", k_validate_edges, grid_for(m, kBlock, 8, d), kBlock, 0, s, n,
+             m, src, dst, d_count);
+  return CCL_OK;
+}
+
+// ---------------------------------------------------------------- probe
+
+// Streaming copy, 16 bytes per lane per iteration; the tail byte by byte.
+__global__ void __launch_bounds__(kBlock)
+    k_probe_copy(const int4* __restrict__ in, int4* __restrict__ out, int64_t n16,
+                 const uint8_t* __restrict__ in_b, uint8_t* __restrict__ out_b, int64_t tail) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int64_t i = tid; i < n16; i += stride) out[i] = in[i];
+  if (tid < tail) out_b[tid] = in_b[tid];
+}
+
+ccl_status launch_probe_copy(const void* in, void* out, size_t bytes, hipStream_t s,
+                             const DeviceInfo& d) {
+  if (bytes == 0) return CCL_OK;
+  const int64_t n16 = (int64_t)(bytes / 16), tail = (int64_t)(bytes % 16);
+  const uint8_t* ib = static_cast<const uint8_t*>(in) + n16 * 16;
+  uint8_t* ob = static_cast<uint8_t*>(out) + n16 * 16;
+  CCL_LAUNCH("ccl_probe_copy", k_probe_copy, grid_for(n16 > 0 ? n16 : 1, kBlock, 8, d), kBlock, 0,
+             s, static_cast<const int4*>(in), static_cast<int4*>(out), n16, ib, ob, tail);
+  return CCL_OK;
+}
+
+}  // namespace ccl

@@ -1,0 +1,119 @@
+// Device-side union-find primitives of the labeling (paper, sections 2-3).
+//
+// The label array is the union-find forest: label[x] <= x always, and
+// label[x] == x marks a root.  Two facts make the lock-free scheme correct
+// under any interleaving of threads:
+//   * every write to label[x] stores a member of x's cluster that is smaller
+//     than the value it replaces or equal to an ancestor of it, so a stale
+//     read is still a valid (older) link and root chases always terminate
+//     (indices strictly decrease along a chain);
+//   * the atomicMin loop of Algorithm 1 re-joins every link it displaces.
+// Hence plain (possibly stale, cached) loads are used for root chases and
+// only the atomicMin has to be coherent across the chip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccl {
+
+// ---------------------------------------------------------------- global
+
+// Ordinary cached global load/store of a label.  Wavefront-scope relaxed
+// atomics compile to plain global_load/global_store on gfx950; using them
+// keeps the compiler from caching a value across iterations of a chase.
+__device__ __forceinline__ int32_t lab_ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void lab_st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Device-coherent atomicMin returning the previous value.
+__device__ __forceinline__ int32_t lab_min(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The analysis chase (sections 2-3): follow label until label[r] == r.
+__device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
+  int32_t p = lab_ld(label + x);
+  while (p != x) {
+    x = p;
+    p = lab_ld(label + x);
+  }
+  return x;
+}
+
+// Join roots r1, r2 (any members work; roots save atomics): the label
+// reduction loop of Algorithm 1.  Order so that r1 > r2, then
+// old = atomicMin(label[r1], r2):
+//   old == r2  : the link already existed                         -> done
+//   old == r1  : r1 was a root and now points at r2               -> done
+//                (one atomic earlier than the printed loop, which would
+//                 repeat the atomicMin and read back r2)
+//   otherwise  : r1's previous link `old` was replaced; old and r2
+//                must now be joined -- continue with the pair (old, r2).
+// max(r1, r2) strictly decreases each round, so the loop terminates.
+__device__ __forceinline__ void join_roots(int32_t* label, int32_t r1, int32_t r2) {
+  while (r1 != r2) {
+    if (r1 < r2) {
+      int32_t t = r1;
+      r1 = r2;
+      r2 = t;
+    }
+    int32_t old = lab_min(label + r1, r2);
+    if (old == r2 || old == r1) break;
+    r1 = old;
+  }
+}
+
+// Step (iii) for one bond (a, b): roots of both ends, then Algorithm 1.
+// Bonds whose ends already share a root issue no atomic.
+__device__ __forceinline__ void unite(int32_t* label, int32_t a, int32_t b) {
+  int32_t r1 = find_root(label, a);
+  int32_t r2 = find_root(label, b);
+  if (r1 != r2) join_roots(label, r1, r2);
+}
+
+// ---------------------------------------------------------------- LDS
+
+__device__ __forceinline__ int32_t lds_ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t lds_min(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root chase in LDS with path halving (x -> grandparent).  The racy store is
+// safe for the reasons given at the top of this file: it writes an ancestor.
+__device__ __forceinline__ int32_t lds_find(int32_t* par, int32_t x) {
+  int32_t p = lds_ld(par + x);
+  while (p != x) {
+    int32_t g = lds_ld(par + p);
+    if (g == p) return p;
+    lds_st(par + x, g);
+    x = g;
+    p = lds_ld(par + x);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void lds_unite(int32_t* par, int32_t a, int32_t b) {
+  int32_t r1 = lds_find(par, a);
+  int32_t r2 = lds_find(par, b);
+  while (r1 != r2) {
+    if (r1 < r2) {
+      int32_t t = r1;
+      r1 = r2;
+      r2 = t;
+    }
+    int32_t old = lds_min(par + r1, r2);
+    if (old == r2 || old == r1) break;
+    r1 = old;
+  }
+}
+
+}  // namespace ccl

@@ -1,0 +1,108 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+include/ccl.h declares, and rejects bad arguments on the host before any HIP
+call (no compute call runs here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccl.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(ccl_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1603_08357_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    import paper_1603_08357_amd as ccl
+    return ccl._lib
+
+
+def test_header_parses():
+    names = declared_functions()
+    for must in ("ccl_label", "ccl_label_csr", "ccl_label_batched", "ccl_plan_create",
+                 "ccl_validate_edges", "ccl_status_string"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1603_08357_amd import library_path
+    out = subprocess.run(["nm", "-D", "--defined-only", library_path], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        getattr(lib, n)
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "ccl.h"\nint main(void){return ccl_version()>0?0:1;}\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    "-c", str(src), "-o", str(tmp_path / "t.o")], check=True)
+
+
+def test_status_strings(lib):
+    for code in range(6):
+        assert lib.ccl_status_string(code).startswith(b"CCL_")
+    assert lib.ccl_version() == 100
+
+
+def test_host_side_argument_errors(lib):
+    INVALID = 1
+    assert lib.ccl_label(-1, 0, None, None, None, None, None) == INVALID
+    assert lib.ccl_label(2**31, 0, None, None, None, None, None) == INVALID
+    assert lib.ccl_label(5, 3, None, None, None, ctypes.c_void_p(64), None) == INVALID
+    assert lib.ccl_label(5, 0, None, None, None, None, None) == INVALID  # labels NULL
+    assert lib.ccl_label(0, 0, None, None, None, None, None) == 0  # nothing to do
+    # bonds but no sites: no valid id exists
+    assert lib.ccl_label(0, 2, ctypes.c_void_p(64), ctypes.c_void_p(128), None,
+                         ctypes.c_void_p(256), None) == INVALID
+    # labels overlapping src
+    assert lib.ccl_label(10, 10, ctypes.c_void_p(4096), ctypes.c_void_p(8192), None,
+                         ctypes.c_void_p(4096 + 8), None) == INVALID
+    # CSR: > one tile needs a workspace of the right size and alignment
+    n = 100_000
+    assert lib.ccl_label_csr_workspace_size(n) == ((n + 63) // 64) * 8
+    assert lib.ccl_label_csr_workspace_size(0) == 0
+    args = (n, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), None, ctypes.c_void_p(1 << 28))
+    assert lib.ccl_label_csr(*args, None, 0, None) == INVALID
+    assert lib.ccl_label_csr(*args, ctypes.c_void_p(1 << 30), 8, None) == INVALID
+    assert lib.ccl_label_csr(*args, ctypes.c_void_p((1 << 30) + 4), 1 << 20, None) == INVALID
+    assert lib.ccl_label_csr(-3, None, None, None, None, None, 0, None) == INVALID
+    assert lib.ccl_label_csr(0, None, None, None, None, None, 0, None) == 0
+
+
+def test_plan_argument_errors(lib):
+    INVALID = 1
+    plan = ctypes.c_void_p()
+    so = (ctypes.c_int64 * 3)(0, 10, 5)  # decreasing
+    bo = (ctypes.c_int64 * 3)(0, 4, 8)
+    assert lib.ccl_plan_create(2, so, bo, None, ctypes.byref(plan)) == INVALID
+    so = (ctypes.c_int64 * 3)(1, 10, 20)  # does not start at 0
+    assert lib.ccl_plan_create(2, so, bo, None, ctypes.byref(plan)) == INVALID
+    assert lib.ccl_plan_create(-1, so, bo, None, ctypes.byref(plan)) == INVALID
+    assert lib.ccl_plan_create(1, None, None, None, ctypes.byref(plan)) == INVALID
+    assert lib.ccl_label_batched(None, None, None, None, None, None) == INVALID
+    assert lib.ccl_plan_destroy(None) == 0
+
+
+def test_validation_argument_errors(lib):
+    INVALID = 1
+    bad = ctypes.c_int64()
+    assert lib.ccl_validate_edges(-1, 0, None, None, ctypes.byref(bad), None) == INVALID
+    assert lib.ccl_validate_edges(5, 3, None, None, ctypes.byref(bad), None) == INVALID
+    assert lib.ccl_validate_edges(5, 0, None, None, ctypes.byref(bad), None) == 0
+    assert bad.value == 0
+    assert lib.ccl_validate_csr(5, None, None, 0, ctypes.byref(bad), None) == INVALID

@@ -1,0 +1,320 @@
+"""GPU parity: labels from libccl.so (through the C ABI) must equal the CPU
+oracle's bit for bit -- the labeling is integer and its result unique (each
+cluster labelled by its minimum site number), so no tolerance applies."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from conftest import read_golden
+from test_oracle import check_invariants, load_cases
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1603_08357_amd as lib
+    return lib
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_edges(ccl, n, src, dst, occ=None):
+    _say(f"ccl_label n={n} m={len(src)} occ={'none' if occ is None else 'mask'}")
+    out = ccl.label(dev(src), dev(dst), n, None if occ is None else dev(occ))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def gpu_csr(ccl, row_ptr, col, occ=None):
+    _say(f"ccl_label_csr n={len(row_ptr) - 1} m={len(col)}")
+    out = ccl.label_csr(dev(row_ptr), dev(col), None if occ is None else dev(occ))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------ small graphs
+
+@pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
+def test_hand_worked_cases(ccl, case):
+    b = case["bonds"]
+    src = np.array([x[0] for x in b], np.int32)
+    dst = np.array([x[1] for x in b], np.int32)
+    occ = np.array([x[2] for x in b], np.uint8)
+    assert gpu_edges(ccl, case["n"], src, dst, occ).tolist() == case["expect"]
+
+
+def test_exhaustive_k5(ccl):
+    pairs = list(itertools.combinations(range(5), 2))
+    s = np.array([p[0] for p in pairs], np.int32)
+    d = np.array([p[1] for p in pairs], np.int32)
+    ds, dd = dev(s), dev(d)
+    _say("exhaustive K5 (1024 masks)")
+    for mask in range(1 << len(pairs)):
+        occ = np.array([(mask >> j) & 1 for j in range(len(pairs))], np.uint8)
+        got = ccl.label(ds if mask & 1 else dd, dd if mask & 1 else ds, 5, dev(occ)).cpu().numpy()
+        want = oracle.label_edges(5, s, d, occ)
+        assert got.tolist() == want.tolist(), mask
+
+
+@pytest.mark.parametrize("n,m,seed", [(1, 0, 0), (1, 5, 1), (2, 1, 2), (7, 3, 3), (63, 40, 4),
+                                      (65, 200, 5), (1000, 999, 6), (4099, 6000, 7),
+                                      (100_003, 150_001, 8), (1_000_001, 700_001, 9)])
+def test_random_multigraphs(ccl, n, m, seed):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    occ = (rng.random(m) < 0.6).astype(np.uint8)
+    got = gpu_edges(ccl, n, src, dst, occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(n, src, dst, occ))
+    check_invariants(got, n, src, dst, occ)
+
+
+def test_empty_and_degenerate(ccl):
+    e = np.zeros(0, np.int32)
+    assert gpu_edges(ccl, 1, e, e).tolist() == [0]
+    np.testing.assert_array_equal(gpu_edges(ccl, 1000, e, e), np.arange(1000))
+    out = ccl.label(torch.zeros(0, dtype=torch.int32, device="cuda"),
+                    torch.zeros(0, dtype=torch.int32, device="cuda"), 0)
+    assert out.numel() == 0
+    src, dst = gen.triangle_edges(33)
+    np.testing.assert_array_equal(gpu_edges(ccl, 33 * 33, src, dst, np.zeros(len(src), np.uint8)),
+                                  np.arange(33 * 33))
+    assert not gpu_edges(ccl, 33 * 33, src, dst).any()  # NULL mask: all occupied
+
+
+# ------------------------------------------------------------ workloads
+
+def test_config1_honeycomb_l256(ccl):
+    """Honeycomb L=256 periodic, p = 0.6527, edge list."""
+    g = gen.honeycomb_realization(256, 0.6527, 1)
+    got = gpu_edges(ccl, g.n_sites, g.src, g.dst, g.occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ))
+    check_invariants(got, g.n_sites, g.src, g.dst, g.occ)
+
+
+@pytest.mark.parametrize("L,p", [(181, 0.3473), (300, 0.1736), (300, 0.5209), (512, 0.3473)])
+def test_triangle_csr_multi_tile(ccl, L, p):
+    """Several 32768-site tiles and a ragged last tile."""
+    g = gen.triangle_csr_realization(L, p, L)
+    got = gpu_csr(ccl, g.row_ptr, g.col, g.occ)
+    np.testing.assert_array_equal(got, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ))
+
+
+@pytest.mark.parametrize("p", [0.3473, 0.1736, 0.5209])
+def test_config2_triangle_l8192_csr(ccl, p):
+    """Full size: triangle L=8192 periodic (67,108,864 sites), half-CSR."""
+    g = gen.triangle_csr_realization(8192, p, 2)
+    got = gpu_csr(ccl, g.row_ptr, g.col, g.occ)
+    want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_csr_forms(ccl):
+    # honeycomb half-CSR: every second row empty
+    L = 200
+    row_ptr, col = gen.honeycomb_csr(L)
+    occ = gen.bernoulli(4, len(col), 0.6527)
+    np.testing.assert_array_equal(gpu_csr(ccl, row_ptr, col, occ),
+                                  oracle.label_csr(2 * L * L, row_ptr, col, occ))
+    # ragged degrees, random columns, both orientations listed
+    rng = np.random.default_rng(11)
+    n = 150_001
+    deg = rng.integers(0, 9, n)
+    rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    c = rng.integers(0, n, rp[-1]).astype(np.int32)
+    o = (rng.random(rp[-1]) < 0.3).astype(np.uint8)
+    np.testing.assert_array_equal(gpu_csr(ccl, rp, c, o), oracle.label_csr(n, rp, c, o))
+    np.testing.assert_array_equal(gpu_csr(ccl, rp, c, None), oracle.label_csr(n, rp, c, None))
+    # a single tile needs no workspace
+    small = gen.triangle_csr_realization(100, 0.4, 5)
+    out = ccl.label_csr(dev(small.row_ptr), dev(small.col), dev(small.occ),
+                        workspace=torch.empty(8, dtype=torch.uint8, device="cuda"))
+    np.testing.assert_array_equal(out.cpu().numpy(),
+                                  oracle.label_csr(small.n_sites, small.row_ptr, small.col, small.occ))
+
+
+@pytest.mark.parametrize("p", [0.45, 0.5, 0.55])
+def test_config3_random_3_regular(ccl, p):
+    """Bethe substitute: random 3-regular N = 2^24, random position."""
+    g = gen.bethe_random_regular(1 << 24, 3, p, 3)
+    got = gpu_edges(ccl, g.n_sites, g.src, g.dst, g.occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ))
+
+
+@pytest.mark.parametrize("random_position", [False, True])
+def test_cayley_tree(ccl, random_position):
+    g = gen.cayley_realization(18, 0.75, 6, random_position)
+    got = gpu_edges(ccl, g.n_sites, g.src, g.dst, g.occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ))
+    assert len(np.unique(got)) == g.n_sites - int(g.occ.sum())
+
+
+# ------------------------------------------------------------ adversarial
+
+def test_star_hub_last(ccl):
+    """Every union hits one root: 10^6 leaves, hub = N - 1."""
+    n = 1_000_001
+    leaves = np.arange(n - 1, dtype=np.int32)
+    hub = np.full(n - 1, n - 1, np.int32)
+    occ = (leaves % 7 != 3).astype(np.uint8)
+    got = gpu_edges(ccl, n, hub, leaves, occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(n, hub, leaves, occ))
+
+
+def test_descending_path_1e7(ccl):
+    n = 10_000_000
+    src = np.arange(n - 1, 0, -1, dtype=np.int32)
+    dst = src - 1
+    got = gpu_edges(ccl, n, src, dst)
+    assert not got.any()
+
+
+def test_complete_graph_k2000(ccl):
+    k = 2000
+    iu = np.triu_indices(k, 1)
+    src, dst = iu[1].astype(np.int32), iu[0].astype(np.int32)
+    rng = np.random.default_rng(2)
+    perm = rng.permutation(k).astype(np.int32)
+    got = gpu_edges(ccl, k, perm[src], perm[dst])
+    assert not got.any()
+
+
+def test_duplicated_bonds(ccl):
+    g = gen.honeycomb_realization(64, 0.6, 7)
+    reps = 1000
+    src = np.tile(g.src, reps)
+    dst = np.tile(g.dst, reps)
+    occ = np.tile(g.occ, reps)
+    got = gpu_edges(ccl, g.n_sites, src, dst, occ)
+    np.testing.assert_array_equal(got, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ))
+
+
+def test_repeat_runs_identical(ccl):
+    g = gen.triangle_csr_realization(1024, 0.3473, 12)
+    want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+    rp, c, o = dev(g.row_ptr), dev(g.col), dev(g.occ)
+    out = torch.empty(g.n_sites, dtype=torch.int32, device="cuda")
+    ws = torch.empty(ccl.csr_workspace_bytes(g.n_sites), dtype=torch.uint8, device="cuda")
+    _say("csr repeat x50")
+    for _ in range(50):
+        ccl.label_csr(rp, c, o, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
+# ------------------------------------------------------------ batches
+
+def _batch(specs):
+    site_off, bond_off, src, dst, occ = gen.batch_arrays(specs)
+    return site_off, bond_off, src, dst, occ
+
+
+@pytest.mark.parametrize("tuning", [None, dict(small_sites=-1), dict(block_threads=256,
+                                                                    blocks_per_cu=2,
+                                                                    bonds_per_chunk=4096,
+                                                                    sites_per_chunk=2048)])
+def test_batched_matches_oracle(ccl, tuning):
+    specs = gen.batch_specs(96, base_seed=21, ls=(8, 16, 64, 128, 256))
+    specs.append(gen.InstanceSpec("triangle", 1, 0.3, 5))  # one site, three self-loops
+    site_off, bond_off, src, dst, occ = _batch(specs)
+    want = oracle.label_batched(site_off, bond_off, src, dst, occ)
+    plan = ccl.Plan(site_off, bond_off, tuning)
+    _say(f"batched K={len(specs)} sites={site_off[-1]} tuning={plan.tuning.as_dict()}")
+    out = plan.label(dev(src), dev(dst), dev(occ))
+    torch.cuda.synchronize()
+    assert plan.check() == 0
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+    # second launch on the same plan and buffers
+    out2 = plan.label(dev(src), dev(dst), dev(occ))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out2.cpu().numpy(), want)
+    # the per-instance schedule gives the same labels
+    base = ccl.label_batched_per_instance(site_off, bond_off, dev(src), dev(dst), dev(occ))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(base.cpu().numpy(), want)
+    plan.close()
+
+
+def test_batched_with_empty_instances(ccl):
+    site_off = np.array([0, 0, 5, 5, 105], np.int64)
+    bond_off = np.array([0, 0, 0, 3, 3 + 150], np.int64)
+    rng = np.random.default_rng(3)
+    src = np.concatenate([np.zeros(3), rng.integers(0, 100, 150)]).astype(np.int32)
+    dst = np.concatenate([np.zeros(3), rng.integers(0, 100, 150)]).astype(np.int32)
+    occ = (rng.random(153) < 0.5).astype(np.uint8)
+    # instance 2 has bonds but no sites: rejected
+    with pytest.raises(ccl.CclError):
+        ccl.Plan(site_off, bond_off)
+    bond_off = np.array([0, 0, 0, 0, 150], np.int64)
+    src, dst, occ = src[3:], dst[3:], occ[3:]
+    want = oracle.label_batched(site_off, bond_off, src, dst, occ)
+    plan = ccl.Plan(site_off, bond_off)
+    out = plan.label(dev(src), dev(dst), dev(occ))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
+def test_batched_graph_replay(ccl):
+    """Capture the batched launch in a HIP graph, replay it several times with
+    eager work in between, and check every replay."""
+    specs = gen.batch_specs(40, base_seed=5, ls=(16, 64, 128))
+    site_off, bond_off, src, dst, occ = _batch(specs)
+    want = oracle.label_batched(site_off, bond_off, src, dst, occ)
+    plan = ccl.Plan(site_off, bond_off)
+    ds, dd, do = dev(src), dev(dst), dev(occ)
+    out = torch.empty(int(site_off[-1]), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.label(ds, dd, do, out=out, stream=s)  # warm-up outside the graph
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    _say("batched graph capture")
+    with torch.cuda.graph(g, stream=s):
+        plan.label(ds, dd, do, out=out, stream=s)
+    for r in range(4):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want, err_msg=f"replay {r}")
+        assert plan.check() == 0
+
+
+# ------------------------------------------------------------ checks & errors
+
+def test_validate(ccl):
+    src = dev(np.array([0, 1, 5, -1, 2], np.int32))
+    dst = dev(np.array([1, 2, 0, 0, 9], np.int32))
+    assert ccl.validate_edges(src, dst, 5) == 3
+    assert ccl.validate_edges(src[:2], dst[:2], 5) == 0
+    rp = dev(np.array([0, 2, 1, 4], np.int32))
+    col = dev(np.array([1, 2, 3, 0], np.int32))
+    assert ccl.validate_csr(rp, col) == 2  # one decreasing step, one id == n
+    g = gen.triangle_csr_realization(50, 0.3, 1)
+    assert ccl.validate_csr(dev(g.row_ptr), dev(g.col)) == 0
+
+
+def test_argument_errors(ccl):
+    e = dev(np.zeros(4, np.int32))
+    with pytest.raises(ccl.CclError):  # labels alias an input
+        ccl.label(e, e, 4, out=e)
+    g = gen.triangle_csr_realization(200, 0.3, 1)
+    with pytest.raises(ccl.CclError):  # workspace too small for 40000 sites
+        ccl.label_csr(dev(g.row_ptr), dev(g.col), dev(g.occ),
+                      workspace=torch.empty(8, dtype=torch.uint8, device="cuda"))
