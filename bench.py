@@ -190,6 +190,111 @@ def probe_copy(nbytes=1 << 30):
     return {"bytes": 2 * nbytes, "ms": ms, "GBs": round(2 * nbytes / ms / 1e6, 1)}
 
 
+def upload_batch(specs, chunk=64):
+    """Generate a batch instance by instance on the host (in chunks) and copy
+    it into device arrays; host memory stays at one chunk."""
+    import numpy as np
+    import torch
+    import gen
+    site_off, bond_off = gen.batch_offsets(specs)
+    m = int(bond_off[-1])
+    src = torch.empty(m, dtype=torch.int32, device="cuda")
+    dst = torch.empty(m, dtype=torch.int32, device="cuda")
+    occ = torch.empty(m, dtype=torch.uint8, device="cuda")
+    for a in range(0, len(specs), chunk):
+        b = min(a + chunk, len(specs))
+        lo, hi = int(bond_off[a]), int(bond_off[b])
+        hs, hd, ho = np.empty(hi - lo, np.int32), np.empty(hi - lo, np.int32), np.empty(hi - lo, np.uint8)
+        for k in range(a, b):
+            x, y = int(bond_off[k]) - lo, int(bond_off[k + 1]) - lo
+            gen.fill_instance(specs[k], hs[x:y], hd[x:y], ho[x:y])
+        src[lo:hi].copy_(torch.from_numpy(hs))
+        dst[lo:hi].copy_(torch.from_numpy(hd))
+        occ[lo:hi].copy_(torch.from_numpy(ho))
+    torch.cuda.synchronize()
+    return site_off, bond_off, src, dst, occ
+
+
+def sample_instances(specs, count=12):
+    """Indices of instances to check: the largest and smallest of each lattice
+    type plus evenly spaced ones."""
+    idx = set(range(0, len(specs), max(1, len(specs) // count)))
+    for kind in ("honeycomb", "triangle"):
+        ks = [k for k, s in enumerate(specs) if s.kind == kind]
+        if ks:
+            idx.add(max(ks, key=lambda k: specs[k].L))
+            idx.add(min(ks, key=lambda k: specs[k].L))
+    return sorted(idx)
+
+
+def check_sampled(specs, site_off, bond_off, labels, idx):
+    """Oracle labels of the sampled instances equal the GPU's."""
+    import numpy as np
+    import gen
+    import oracle
+    for k in idx:
+        s = specs[k]
+        src, dst = (gen.honeycomb_edges if s.kind == "honeycomb" else gen.triangle_edges)(s.L)
+        occ = gen.bernoulli(s.seed, len(src), s.p)
+        want = oracle.label_edges(s.n_sites, src, dst, occ)
+        got = labels[int(site_off[k]):int(site_off[k + 1])].cpu().numpy()
+        if not np.array_equal(got, want):
+            return False
+    return True
+
+
+def bench_batched(n_inst, base_seed, steps, warmup, schedules=(2, 1), check=True):
+    """4096-instance mixed honeycomb / triangle batch: the plan's persistent
+    kernel (captured in a graph and replayed) against one ccl_label call per
+    instance on the same buffers."""
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    t0 = time.perf_counter()
+    specs = gen.batch_specs(n_inst, base_seed)
+    site_off, bond_off, src, dst, occ = upload_batch(specs)
+    n, m = int(site_off[-1]), int(bond_off[-1])
+    log(f"batch of {n_inst}: {n} sites, {m} bonds, uploaded in {time.perf_counter() - t0:.1f}s")
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    res = {"instances": n_inst, "sites": n, "bonds": m,
+           "resident_GB": round((9 * m + 4 * n) / 1e9, 2)}
+    idx = sample_instances(specs)
+    for sched in schedules:
+        plan = ccl.Plan(site_off, bond_off, dict(schedule=sched))
+        with torch.cuda.stream(stream):
+            plan.label(src, dst, occ, out=out, stream=stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            plan.label(src, dst, occ, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ms, _ = time_steps(graph.replay, steps, warmup, torch.cuda.current_stream())
+        name = "fused" if sched == 1 else "phased"
+        rec = {"ms": round(ms, 4), "Gsites_s": round(n / (ms * 1e-3) / 1e9, 3),
+               "path_hbm_frac": round(path_bytes_edges(n, m) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "plan_error": plan.check()}
+        if check:
+            rec["sampled_instances_match_oracle"] = check_sampled(specs, site_off, bond_off, out, idx)
+        kern = traced_kernels(lambda: plan.label(src, dst, occ, out=out), 2)
+        rec["kernels"] = {k: round(v["mean_ms"], 4) for k, v in kern.items()}
+        res[f"batched_{name}"] = rec
+        plan.close()
+        del graph
+    base_steps = max(1, min(3, steps))
+    fn = lambda: ccl.label_batched_per_instance(site_off, bond_off, src, dst, occ, out=out)
+    ms, _ = time_steps(fn, base_steps, 1, torch.cuda.current_stream())
+    res["per_instance"] = {"ms": round(ms, 4), "Gsites_s": round(n / (ms * 1e-3) / 1e9, 3),
+                           "launches": 3 * n_inst}
+    if check:
+        res["per_instance"]["sampled_instances_match_oracle"] = check_sampled(specs, site_off, bond_off, out, idx)
+    best = min(res[k]["ms"] for k in res if k.startswith("batched_"))
+    res["batched_speedup_vs_per_instance"] = round(ms / best, 3)
+    del src, dst, occ, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_oracle_csr(g):
     import oracle
     t0 = time.perf_counter()
@@ -211,6 +316,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", choices=["all", "none"], default="all")
+    ap.add_argument("--batch", type=int, default=4096, help="instances in the batched workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -260,6 +366,10 @@ def main():
         extra["honeycomb_L256"] = {"Gsites_s": round(rh["n"] / (rh["ms"] * 1e-3) / 1e9, 3),
                                    "ms_per_step": round(rh["ms"], 5),
                                    "kernels": {k: round(v["mean_ms"], 5) for k, v in rh["kernels"].items()}}
+        try:
+            extra["batched_4096"] = bench_batched(args.batch, 4, max(3, args.steps // 4), 1)
+        except Exception as e:
+            extra["batched_4096"] = f"failed: {type(e).__name__}: {e}"
         for pp in (0.45, 0.5, 0.55):
             b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
             _, rb = bench_edges(b, args.steps, args.warmup)

@@ -117,6 +117,10 @@ typedef struct {
                               entirely in LDS by one workgroup; 0 = default
                               (fits the LDS of the resident workgroups),
                               negative = never */
+  int32_t schedule;        /* 1 = fused: one persistent launch in which work
+                              items wait for the items they depend on;
+                              2 = phased: init, merge and flatten items as
+                              three launches (no waiting); 0 = default (2) */
 } ccl_tuning;
 
 /*
@@ -150,9 +154,10 @@ ccl_status ccl_plan_get_tuning(ccl_plan plan, ccl_tuning* out);
 ccl_status ccl_plan_check(ccl_plan plan, int32_t* error_host);
 
 /*
- * Label every instance of the plan's layout in one persistent launch (plus a
- * small kernel that resets the plan's counters; no memset node, so the pair
- * can be captured into a HIP graph and replayed).
+ * Label every instance of the plan's layout: a small kernel that resets the
+ * plan's counters (no memset node, so the launches can be captured into a HIP
+ * graph and replayed), then the persistent kernel -- one launch for the fused
+ * schedule, three for the phased one.
  *   src, dst   device int32[total bonds], instance-local ids
  *   occupied   device uint8[total bonds] or NULL
  *   labels_out device int32[total sites]

@@ -41,7 +41,10 @@ class Tuning(ctypes.Structure):
     """ccl_tuning: zero fields take the library defaults."""
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("bonds_per_chunk", ctypes.c_int32), ("sites_per_chunk", ctypes.c_int32),
-                ("small_sites", ctypes.c_int32)]
+                ("small_sites", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+    FUSED = 1
+    PHASED = 2
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

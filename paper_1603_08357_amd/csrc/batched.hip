@@ -1,23 +1,33 @@
-// Batched labeling: many independent instances in one persistent launch.
+// Batched labeling: many independent instances per launch.
 //
 // Each instance runs the three steps of section 3 -- init (i), the Algorithm 1
 // merge over its occupied bonds (iii), flatten (iv) -- split into work items:
-//   SMALL    an instance of at most `small_sites` sites, labelled entirely in
-//            LDS by one workgroup (init, merge and flatten on the LDS copy,
-//            then one coalesced store);
-//   INIT c   sites [c*S, (c+1)*S) of a large instance;
-//   MERGE c  bonds [c*Bc, (c+1)*Bc), after every INIT item of the instance;
+//   SMALL     an instance of at most `small_sites` sites, labelled entirely in
+//             LDS by one workgroup (init, merge and flatten on the LDS copy,
+//             then one coalesced store);
+//   INIT c    sites [c*S, (c+1)*S) of a large instance;
+//   MERGE c   bonds [c*Bc, (c+1)*Bc), after every INIT item of the instance;
 //   FLATTEN c sites [c*S, ...), after every MERGE item of the instance.
-// Workgroups take items in table order from one atomic counter.  An item only
-// waits for items earlier in the table, which were already taken by running
-// workgroups and never wait for later ones, so the schedule cannot deadlock
-// whatever the number of resident workgroups.  Waits are bounded anyway: a
-// wait that exceeds its spin limit sets an error word and gives up, so every
-// wave always exits.
+// Workgroups of a persistent grid take items from an atomic counter.
 //
-// Table order: instances by decreasing size, software-pipelined so that the
-// INIT items of instance s, the MERGE items of instance s-1 and the FLATTEN
-// items of instance s-2 form stage s; SMALL items come last and fill the tail.
+// Two schedules over the same items:
+//   phased : three launches (INIT + SMALL, then MERGE, then FLATTEN); the
+//            kernel boundaries order the steps, no workgroup ever waits.
+//   fused  : one launch; an item waits for the items of its instance it
+//            depends on.  The table puts every such item earlier (instances by
+//            decreasing size, software-pipelined: stage s holds the INIT items
+//            of instance s, the MERGE items of s-1, the FLATTEN items of s-2;
+//            SMALL items last), and items are taken in table order by running
+//            workgroups that never wait for later items, so the wait graph
+//            cannot deadlock whatever the number of resident workgroups.
+//            Publication: every thread fences its own label stores device-wide
+//            before the barrier that precedes the counter increment; the
+//            waiter takes an acquire fence after seeing the count.
+// Fail-safe: waits are bounded; a wait that gives up sets the error word and
+// from then on every item skips its work, and root chases in this file reject
+// a label that points upward or out of range (impossible for valid labels), so
+// the kernel always drains even if a publication went wrong.  The host reads
+// the error word with ccl_plan_check().
 #include <stdlib.h>
 
 #include <algorithm>
@@ -31,6 +41,7 @@
 namespace ccl {
 
 enum : uint32_t { kItemSmall = 0, kItemInit = 1, kItemMerge = 2, kItemFlatten = 3 };
+enum : int32_t { kScheduleDefault = 0, kScheduleFused = 1, kSchedulePhased = 2 };
 
 __host__ __device__ inline uint64_t pack_item(uint32_t inst, uint32_t kind, uint32_t chunk) {
   return ((uint64_t)inst << 32) | ((uint64_t)kind << 30) | chunk;
@@ -42,64 +53,114 @@ struct BatchArgs {
   const uint64_t* items;
   int64_t n_items;
   uint32_t* head;        // next item to take
-  uint32_t* error;       // nonzero: a wait hit its spin limit
-  int32_t* init_done;    // per instance: finished INIT items
-  int32_t* merge_done;   // per instance: finished MERGE items
+  uint32_t* error;       // nonzero: a wait gave up or a chase met an invalid label
+  int32_t* init_done;    // per instance: finished INIT items (fused schedule)
+  int32_t* merge_done;   // per instance: finished MERGE items (fused schedule)
   const int32_t* src;
   const int32_t* dst;
   const uint8_t* occ;
   int32_t* label;
   int32_t sites_per_chunk;
   int32_t bonds_per_chunk;
-  int32_t small_sites;
   uint32_t spin_limit;
+  int32_t fused;
 };
 
 __device__ __forceinline__ int32_t n_chunks(int64_t count, int32_t per) {
   return (int32_t)((count + per - 1) / per);
 }
 
-// Thread 0 waits until *ctr >= need (acquire), then the workgroup proceeds.
-__device__ __forceinline__ void wait_count(const BatchArgs& a, int32_t* ctr, int32_t need) {
+__device__ __forceinline__ void raise_error(uint32_t* error, uint32_t bit) {
+  __hip_atomic_fetch_or(error, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root chase that refuses invalid labels: a valid label never points upward
+// (label[x] <= x), so a chain strictly decreases and stays in [0, n).
+__device__ __forceinline__ int32_t find_root_checked(const int32_t* lab, int32_t x, bool& bad) {
+  int32_t p = lab_ld(lab + x);
+  while (p != x) {
+    if (p > x || p < 0) {
+      bad = true;
+      return x;
+    }
+    x = p;
+    p = lab_ld(lab + x);
+  }
+  return x;
+}
+
+// Algorithm 1 with the same refusal: a returned old value above r1 or below
+// zero cannot come from a valid forest.
+__device__ __forceinline__ void unite_checked(int32_t* lab, int32_t a, int32_t b, bool& bad) {
+  int32_t r1 = find_root_checked(lab, a, bad);
+  int32_t r2 = find_root_checked(lab, b, bad);
+  while (!bad && r1 != r2) {
+    if (r1 < r2) {
+      int32_t t = r1;
+      r1 = r2;
+      r2 = t;
+    }
+    const int32_t old = lab_min(lab + r1, r2);
+    if (old == r2 || old == r1) break;
+    if (old > r1 || old < 0) {
+      bad = true;
+      break;
+    }
+    r1 = old;
+  }
+}
+
+// Fused schedule: thread 0 waits for *ctr >= need; returns false (for the
+// whole workgroup) when it gave up or the launch already failed.
+__device__ bool wait_count(const BatchArgs& a, int32_t* ctr, int32_t need, uint32_t* ok_slot) {
   if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    uint32_t ok = 1, spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
+      }
       if (++spins > a.spin_limit) {
-        __hip_atomic_fetch_or(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        raise_error(a.error, 1u);
+        ok = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *ok_slot = ok;
   }
   __syncthreads();
+  return *ok_slot != 0;
 }
 
-// Every thread's stores are ordered before thread 0's release increment by
-// the barrier; the release makes them visible device-wide.
+// Fused schedule: every thread makes its own stores visible device-wide, the
+// barrier orders all of them before thread 0's increment.
 __device__ __forceinline__ void signal_done(int32_t* ctr) {
+  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_batched_reset(uint32_t* head, uint32_t* error, int32_t* done, int64_t n_done) {
+__global__ void k_batched_reset(uint32_t* head, int64_t n_head, int32_t* done, int64_t n_done) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid == 0) {
-    *head = 0;
-    *error = 0;
-  }
+  for (int64_t i = tid; i < n_head; i += stride) head[i] = 0;
   for (int64_t i = tid; i < n_done; i += stride) done[i] = 0;
 }
 
 __global__ void k_batched(BatchArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ uint32_t item_slot;
+  __shared__ uint32_t ok_slot;
+  __shared__ uint32_t bad_any;
   for (;;) {
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
       item_slot = __hip_atomic_fetch_add(a.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bad_any = 0;
+    }
     __syncthreads();
     const uint32_t it = item_slot;
-    __syncthreads();  // item_slot is rewritten on the next round
     if ((int64_t)it >= a.n_items) break;
     const uint64_t w = a.items[it];
     const uint32_t k = (uint32_t)(w >> 32);
@@ -113,6 +174,7 @@ __global__ void k_batched(BatchArgs a) {
     const int32_t* src = a.src + b0;
     const int32_t* dst = a.dst + b0;
     const uint8_t* occ = a.occ ? a.occ + b0 : nullptr;
+    bool bad = false;
 
     if (kind == kItemSmall) {
       for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = i;
@@ -121,30 +183,42 @@ __global__ void k_batched(BatchArgs a) {
         if (occ == nullptr || occ[b] != 0) lds_unite(lds, src[b], dst[b]);
       __syncthreads();
       for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lab[i] = lds_find(lds, i);
-      __syncthreads();  // lds is reused by the next item
     } else if (kind == kItemInit) {
       const int32_t lo = c * a.sites_per_chunk;
       const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
       for (int32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) lab[i] = i;
-      signal_done(a.init_done + k);
+      if (a.fused) signal_done(a.init_done + k);
     } else if (kind == kItemMerge) {
-      wait_count(a, a.init_done + k, n_chunks(n, a.sites_per_chunk));
-      const int64_t lo = (int64_t)c * a.bonds_per_chunk;
-      const int64_t hi = min(lo + a.bonds_per_chunk, m);
-      for (int64_t b = lo + threadIdx.x; b < hi; b += blockDim.x)
-        if (occ == nullptr || occ[b] != 0) unite(lab, src[b], dst[b]);
-      signal_done(a.merge_done + k);
+      const bool go =
+          !a.fused || wait_count(a, a.init_done + k, n_chunks(n, a.sites_per_chunk), &ok_slot);
+      if (go) {
+        const int64_t lo = (int64_t)c * a.bonds_per_chunk;
+        const int64_t hi = min(lo + a.bonds_per_chunk, m);
+        for (int64_t b = lo + threadIdx.x; b < hi && !bad; b += blockDim.x)
+          if (occ == nullptr || occ[b] != 0) unite_checked(lab, src[b], dst[b], bad);
+      }
+      if (a.fused) signal_done(a.merge_done + k);
     } else {
-      wait_count(a, a.merge_done + k, n_chunks(m, a.bonds_per_chunk));
-      const int32_t lo = c * a.sites_per_chunk;
-      const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
-      for (int32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const int32_t p = lab_ld(lab + i);
-        if (p == i) continue;
-        const int32_t g = lab_ld(lab + p);
-        if (g != p) lab_st(lab + i, find_root(lab, g));
+      const bool go =
+          !a.fused || wait_count(a, a.merge_done + k, n_chunks(m, a.bonds_per_chunk), &ok_slot);
+      if (go) {
+        const int32_t lo = c * a.sites_per_chunk;
+        const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
+        for (int32_t i = lo + threadIdx.x; i < hi && !bad; i += blockDim.x) {
+          const int32_t p = lab_ld(lab + i);
+          if (p == i) continue;
+          if (p > i || p < 0) {
+            bad = true;
+            break;
+          }
+          const int32_t r = find_root_checked(lab, p, bad);
+          if (!bad && r != p) lab_st(lab + i, r);
+        }
       }
     }
+    if (bad) bad_any = 1;  // benign race: every writer stores 1
+    __syncthreads();       // item_slot, ok_slot, bad_any and lds are rewritten next round
+    if (threadIdx.x == 0 && bad_any) raise_error(a.error, 2u);
   }
 }
 
@@ -158,13 +232,14 @@ struct ccl_plan_s {
   ccl_tuning tuning{};
   int64_t total_sites = 0, total_bonds = 0;
   int64_t n_items = 0;
+  int64_t phase_end[3] = {0, 0, 0};  // phased schedule: items [end[p-1], end[p]) form phase p
   unsigned grid = 0;
   void* dev_block = nullptr;  // one allocation holding every table below
   int64_t* d_site_off = nullptr;
   int64_t* d_bond_off = nullptr;
   uint64_t* d_items = nullptr;
-  uint32_t* d_head = nullptr;  // head, error, then the done counters
-  int32_t* d_done = nullptr;   // init_done[K], merge_done[K]
+  uint32_t* d_ctl = nullptr;  // [0..2] queue heads, [3] error word
+  int32_t* d_done = nullptr;  // init_done[K], merge_done[K]
 };
 
 using namespace ccl;
@@ -180,17 +255,19 @@ static ccl_tuning resolve_tuning(const ccl_tuning* t, const DeviceInfo& d) {
     r.small_sites = 0;  // LDS path off
   } else if (r.small_sites == 0) {
     // one small instance per resident workgroup must fit the CU's LDS
-    const int cap = (160 * 1024) / r.blocks_per_cu / 4;
-    r.small_sites = std::min(cap, std::min(8192, d.max_lds_per_block / 4));
+    const int cap = (160 * 1024) / r.blocks_per_cu / 4 - 64;
+    r.small_sites = std::min(cap, std::min(8192, d.max_lds_per_block / 4 - 64));
   }
+  if (r.schedule == kScheduleDefault) r.schedule = kSchedulePhased;
   return r;
 }
 
 static bool tuning_ok(const ccl_tuning& t, const DeviceInfo& d) {
   if (t.block_threads % 64 != 0 || t.block_threads > 1024) return false;
   if (t.blocks_per_cu > 32 || t.bonds_per_chunk <= 0 || t.sites_per_chunk <= 0) return false;
-  if ((int64_t)t.small_sites * 4 > d.max_lds_per_block) return false;
-  if ((int64_t)t.small_sites * 4 * t.blocks_per_cu > 160 * 1024) return false;
+  if ((int64_t)t.small_sites * 4 + 64 > d.max_lds_per_block) return false;
+  if (((int64_t)t.small_sites * 4 + 64) * t.blocks_per_cu > 160 * 1024) return false;
+  if (t.schedule != kScheduleFused && t.schedule != kSchedulePhased) return false;
   return true;
 }
 
@@ -221,7 +298,7 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
       return CCL_ERR_INVALID_VALUE;
   }
 
-  // work-item table
+  // instances by decreasing size; small ones are labelled in LDS
   std::vector<int32_t> order(n_inst);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -231,36 +308,39 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   for (int32_t k : order) {
     const int64_t n = site_off_host[k + 1] - site_off_host[k];
     if (n == 0) continue;
-    if (n <= t.small_sites)
-      small.push_back(k);
-    else
-      large.push_back(k);
+    (n <= t.small_sites ? small : large).push_back(k);
   }
+  auto n_init = [&](int32_t k) {
+    return (site_off_host[k + 1] - site_off_host[k] + t.sites_per_chunk - 1) / t.sites_per_chunk;
+  };
+  auto n_merge = [&](int32_t k) {
+    return (bond_off_host[k + 1] - bond_off_host[k] + t.bonds_per_chunk - 1) / t.bonds_per_chunk;
+  };
+  auto emit = [](std::vector<uint64_t>& v, int32_t k, uint32_t kind, int64_t count) {
+    for (int64_t c = 0; c < count; ++c) v.push_back(pack_item(k, kind, (uint32_t)c));
+  };
   std::vector<uint64_t> items;
-  const int64_t L = (int64_t)large.size();
-  for (int64_t stage = 0; stage < L + 2; ++stage) {
-    if (stage < L) {
-      const int32_t k = large[stage];
-      const int64_t n = site_off_host[k + 1] - site_off_host[k];
-      for (int64_t c = 0; c < (n + t.sites_per_chunk - 1) / t.sites_per_chunk; ++c)
-        items.push_back(pack_item(k, kItemInit, (uint32_t)c));
+  int64_t phase_end[3] = {0, 0, 0};
+  if (t.schedule == kScheduleFused) {
+    const int64_t L = (int64_t)large.size();
+    for (int64_t s = 0; s < L + 2; ++s) {
+      if (s < L) emit(items, large[s], kItemInit, n_init(large[s]));
+      if (s >= 1 && s - 1 < L) emit(items, large[s - 1], kItemMerge, n_merge(large[s - 1]));
+      if (s >= 2 && s - 2 < L && n_merge(large[s - 2]) > 0)
+        emit(items, large[s - 2], kItemFlatten, n_init(large[s - 2]));
     }
-    if (stage >= 1 && stage - 1 < L) {
-      const int32_t k = large[stage - 1];
-      const int64_t m = bond_off_host[k + 1] - bond_off_host[k];
-      for (int64_t c = 0; c < (m + t.bonds_per_chunk - 1) / t.bonds_per_chunk; ++c)
-        items.push_back(pack_item(k, kItemMerge, (uint32_t)c));
-    }
-    if (stage >= 2 && stage - 2 < L) {
-      const int32_t k = large[stage - 2];
-      const int64_t n = site_off_host[k + 1] - site_off_host[k];
-      const int64_t m = bond_off_host[k + 1] - bond_off_host[k];
-      if (m > 0)
-        for (int64_t c = 0; c < (n + t.sites_per_chunk - 1) / t.sites_per_chunk; ++c)
-          items.push_back(pack_item(k, kItemFlatten, (uint32_t)c));
-    }
+    for (int32_t k : small) emit(items, k, kItemSmall, 1);
+    phase_end[0] = phase_end[1] = phase_end[2] = (int64_t)items.size();
+  } else {
+    for (int32_t k : large) emit(items, k, kItemInit, n_init(k));
+    for (int32_t k : small) emit(items, k, kItemSmall, 1);
+    phase_end[0] = (int64_t)items.size();
+    for (int32_t k : large) emit(items, k, kItemMerge, n_merge(k));
+    phase_end[1] = (int64_t)items.size();
+    for (int32_t k : large)
+      if (n_merge(k) > 0) emit(items, k, kItemFlatten, n_init(k));
+    phase_end[2] = (int64_t)items.size();
   }
-  for (int32_t k : small) items.push_back(pack_item(k, kItemSmall, 0));
   if ((int64_t)items.size() >= (int64_t)UINT32_MAX) return CCL_ERR_INVALID_VALUE;
 
   ccl_plan p = new (std::nothrow) ccl_plan_s();
@@ -271,13 +351,14 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   p->total_sites = site_off_host[n_inst];
   p->total_bonds = bond_off_host[n_inst];
   p->n_items = (int64_t)items.size();
+  for (int i = 0; i < 3; ++i) p->phase_end[i] = phase_end[i];
   p->grid = (unsigned)(d->cu_count * t.blocks_per_cu);
 
   const size_t off_bytes = sizeof(int64_t) * (size_t)(n_inst + 1);
   const size_t item_bytes = sizeof(uint64_t) * items.size();
-  const size_t ctr_bytes = 256 + sizeof(int32_t) * 2 * (size_t)n_inst;
+  const size_t ctl_bytes = 256 + sizeof(int32_t) * 2 * (size_t)n_inst;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = up(off_bytes) * 2 + up(item_bytes) + up(ctr_bytes);
+  const size_t total = up(off_bytes) * 2 + up(item_bytes) + up(ctl_bytes);
   hipError_t e = hipMalloc(&p->dev_block, total);
   if (e != hipSuccess) {
     delete p;
@@ -287,12 +368,14 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   p->d_site_off = reinterpret_cast<int64_t*>(base);
   p->d_bond_off = reinterpret_cast<int64_t*>(base + up(off_bytes));
   p->d_items = reinterpret_cast<uint64_t*>(base + 2 * up(off_bytes));
-  p->d_head = reinterpret_cast<uint32_t*>(base + 2 * up(off_bytes) + up(item_bytes));
-  p->d_done = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(p->d_head) + 256);
+  p->d_ctl = reinterpret_cast<uint32_t*>(base + 2 * up(off_bytes) + up(item_bytes));
+  p->d_done = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(p->d_ctl) + 256);
   e = hipMemcpy(p->d_site_off, site_off_host, off_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_bond_off, bond_off_host, off_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess && item_bytes)
     e = hipMemcpy(p->d_items, items.data(), item_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->d_ctl, 0, up(ctl_bytes));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(p->dev_block);
     delete p;
@@ -319,7 +402,7 @@ ccl_status ccl_plan_get_tuning(ccl_plan plan, ccl_tuning* out) {
 ccl_status ccl_plan_check(ccl_plan plan, int32_t* error_host) {
   if (plan == nullptr || error_host == nullptr) return CCL_ERR_INVALID_VALUE;
   uint32_t v = 0;
-  hipError_t e = hipMemcpy(&v, plan->d_head + 1, sizeof(v), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpy(&v, plan->d_ctl + 3, sizeof(v), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e);
   *error_host = (int32_t)v;
   return CCL_OK;
@@ -339,16 +422,14 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
   if (d->device != plan->device) return CCL_ERR_INVALID_VALUE;
   if (plan->n_items == 0) return CCL_OK;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n_done = 2 * (int64_t)plan->n_inst;
-  CCL_LAUNCH("ccl_batched_reset", k_batched_reset, grid_for(n_done + 1, 256, 4, *d), 256, 0, s,
-             plan->d_head, plan->d_head + 1, plan->d_done, n_done);
+  const bool fused = plan->tuning.schedule == kScheduleFused;
+  const int64_t n_done = fused ? 2 * (int64_t)plan->n_inst : 0;
+  CCL_LAUNCH("ccl_batched_reset", k_batched_reset, grid_for(n_done + 4, 256, 4, *d), 256, 0, s,
+             plan->d_ctl, (int64_t)4, plan->d_done, n_done);
   BatchArgs a;
   a.site_off = plan->d_site_off;
   a.bond_off = plan->d_bond_off;
-  a.items = plan->d_items;
-  a.n_items = plan->n_items;
-  a.head = plan->d_head;
-  a.error = plan->d_head + 1;
+  a.error = plan->d_ctl + 3;
   a.init_done = plan->d_done;
   a.merge_done = plan->d_done + plan->n_inst;
   a.src = src;
@@ -357,10 +438,27 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
   a.label = labels_out;
   a.sites_per_chunk = plan->tuning.sites_per_chunk;
   a.bonds_per_chunk = plan->tuning.bonds_per_chunk;
-  a.small_sites = plan->tuning.small_sites;
-  a.spin_limit = 1u << 22;
+  a.spin_limit = 1u << 20;
+  a.fused = fused ? 1 : 0;
   const unsigned lds = (unsigned)plan->tuning.small_sites * 4;
-  CCL_LAUNCH("ccl_batched", k_batched, plan->grid, plan->tuning.block_threads, lds, s, a);
+  if (fused) {
+    a.items = plan->d_items;
+    a.n_items = plan->n_items;
+    a.head = plan->d_ctl;
+    CCL_LAUNCH("ccl_batched_fused", k_batched, plan->grid, plan->tuning.block_threads, lds, s, a);
+    return CCL_OK;
+  }
+  static const char* names[3] = {"ccl_batched_init", "ccl_batched_merge", "ccl_batched_flatten"};
+  int64_t begin = 0;
+  for (int ph = 0; ph < 3; ++ph) {
+    a.items = plan->d_items + begin;
+    a.n_items = plan->phase_end[ph] - begin;
+    a.head = plan->d_ctl + ph;
+    begin = plan->phase_end[ph];
+    if (a.n_items == 0) continue;
+    const unsigned g = (unsigned)std::min<int64_t>(plan->grid, a.n_items);
+    CCL_LAUNCH(names[ph], k_batched, g, plan->tuning.block_threads, ph == 0 ? lds : 0, s, a);
+  }
   return CCL_OK;
 }
 

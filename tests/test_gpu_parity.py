@@ -225,10 +225,14 @@ def _batch(specs):
     return site_off, bond_off, src, dst, occ
 
 
-@pytest.mark.parametrize("tuning", [None, dict(small_sites=-1), dict(block_threads=256,
-                                                                    blocks_per_cu=2,
-                                                                    bonds_per_chunk=4096,
-                                                                    sites_per_chunk=2048)])
+BATCH_TUNINGS = [None, dict(schedule=2, small_sites=-1),
+                 dict(schedule=2, block_threads=256, blocks_per_cu=2, bonds_per_chunk=4096,
+                      sites_per_chunk=2048),
+                 dict(schedule=1), dict(schedule=1, small_sites=-1, bonds_per_chunk=8192,
+                                        sites_per_chunk=4096)]
+
+
+@pytest.mark.parametrize("tuning", BATCH_TUNINGS, ids=lambda t: str(t))
 def test_batched_matches_oracle(ccl, tuning):
     specs = gen.batch_specs(96, base_seed=21, ls=(8, 16, 64, 128, 256))
     specs.append(gen.InstanceSpec("triangle", 1, 0.3, 5))  # one site, three self-loops
@@ -270,13 +274,14 @@ def test_batched_with_empty_instances(ccl):
     np.testing.assert_array_equal(out.cpu().numpy(), want)
 
 
-def test_batched_graph_replay(ccl):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_batched_graph_replay(ccl, schedule):
     """Capture the batched launch in a HIP graph, replay it several times with
     eager work in between, and check every replay."""
     specs = gen.batch_specs(40, base_seed=5, ls=(16, 64, 128))
     site_off, bond_off, src, dst, occ = _batch(specs)
     want = oracle.label_batched(site_off, bond_off, src, dst, occ)
-    plan = ccl.Plan(site_off, bond_off)
+    plan = ccl.Plan(site_off, bond_off, dict(schedule=schedule))
     ds, dd, do = dev(src), dev(dst), dev(occ)
     out = torch.empty(int(site_off[-1]), dtype=torch.int32, device="cuda")
     s = torch.cuda.Stream()
