@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import sys
@@ -295,6 +297,87 @@ def bench_batched(n_inst, base_seed, steps, warmup, schedules=(2, 1), check=True
     return res
 
 
+def serving_pool(count, base_seed, n_max=10_000_000):
+    """Pre-generated request graphs (random z-regular, random position) in
+    pinned host memory: generating a 10^7-site graph per request would
+    dominate the run, so requests draw from this seeded pool."""
+    import torch
+    import gen
+    reqs = gen.request_trace(count, 1.0, base_seed, n_max=n_max)
+    pool = []
+    for r in reqs:
+        g = gen.request_graph(r)
+        assert g.src.min() >= 0 and max(g.src.max(), g.dst.max()) < g.n_sites and g.dst.min() >= 0
+        pins = tuple(torch.from_numpy(a).pin_memory() for a in (g.src, g.dst, g.occ))
+        pool.append((r, g, pins))
+    return pool
+
+
+def make_jobs(pool, n_req, rate, seed):
+    import gen
+    from paper_1603_08357_amd.serving import Job
+    u = gen.uniform(seed, gen.STREAM_TRACE, 2 * n_req).reshape(n_req, 2)
+    jobs, t = [], 0.0
+    for i in range(n_req):
+        if rate is not None:
+            t += -np.log(1.0 - u[i, 0]) / rate
+        r, g, pins = pool[min(int(u[i, 1] * len(pool)), len(pool) - 1)]
+        j = Job(i, t, g.n_sites, g.src, g.dst, g.occ)
+        j.pinned = pins
+        j.validated = True  # the pool's ids were checked when it was built
+        j.graph = g
+        jobs.append(j)
+    return jobs
+
+
+def bench_serving(pool_size, n_req, seed, budget_gb=64.0, slots=8, check=True):
+    import torch
+    import paper_1603_08357_amd as ccl
+    from paper_1603_08357_amd.serving import GpuExecutor, Scheduler, latency_summary
+    t0 = time.perf_counter()
+    pool = serving_pool(pool_size, seed)
+    log(f"serving pool of {pool_size} graphs in {time.perf_counter() - t0:.1f}s")
+    ex = GpuExecutor(n_streams=slots, max_sites=max(g.n_sites for _, g, _ in pool))
+    budget = int(budget_gb * 1e9)
+    # warm-up: every pool graph once
+    warm = make_jobs(pool, len(pool), None, seed + 1)
+    Scheduler(ex, budget, slots).serve(warm)
+    res = {"pool_graphs": pool_size, "slots": slots, "budget_GB": budget_gb}
+    # saturation: every request present at t = 0
+    jobs = make_jobs(pool, n_req, None, seed + 2)
+    sch = Scheduler(ex, budget, slots)
+    t_a = time.perf_counter()
+    sch.serve(jobs, t0=t_a)
+    t_b = time.perf_counter()
+    sat = latency_summary(jobs, t_a, t_b)
+    res["saturation"] = sat
+    res["peak_admitted_GB"] = round(sch.peak_used / 1e9, 3)
+    rate_sat = sat["throughput_req_s"]
+    for frac in (0.5, 0.8, 0.95):
+        jobs = make_jobs(pool, n_req, frac * rate_sat, seed + 3)
+        sch = Scheduler(ex, budget, slots)
+        t_a = time.perf_counter()
+        sch.serve(jobs, t0=t_a)
+        t_b = time.perf_counter()
+        res[f"load_{frac}"] = latency_summary(jobs, t_a, t_b)
+        res[f"load_{frac}"]["offered_req_s"] = round(frac * rate_sat, 2)
+        assert sch.peak_used <= budget
+    if check:
+        # each request's labels equal the same graph labelled alone
+        alone = {}
+        same = True
+        for j in jobs:
+            key = id(j.graph)
+            if key not in alone:
+                g = j.graph
+                out = ccl.label(torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda(),
+                                g.n_sites, torch.from_numpy(g.occ).cuda())
+                alone[key] = out.cpu().numpy()
+            same = same and np.array_equal(alone[key], j.labels)
+        res["mixed_equals_alone"] = bool(same)
+    return res
+
+
 def cpu_oracle_csr(g):
     import oracle
     t0 = time.perf_counter()
@@ -317,6 +400,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", choices=["all", "none"], default="all")
     ap.add_argument("--batch", type=int, default=4096, help="instances in the batched workload")
+    ap.add_argument("--pool", type=int, default=24, help="graphs in the serving pool")
+    ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -370,6 +455,10 @@ def main():
             extra["batched_4096"] = bench_batched(args.batch, 4, max(3, args.steps // 4), 1)
         except Exception as e:
             extra["batched_4096"] = f"failed: {type(e).__name__}: {e}"
+        try:
+            extra["serving"] = bench_serving(args.pool, args.requests, 5)
+        except Exception as e:
+            extra["serving"] = f"failed: {type(e).__name__}: {e}"
         for pp in (0.45, 0.5, 0.55):
             b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
             _, rb = bench_edges(b, args.steps, args.warmup)

@@ -63,6 +63,29 @@ inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     if (ccl_launch_err_ != hipSuccess) return ::ccl::fail_hip(ccl_launch_err_);         \
   } while (0)
 
+// Workgroups of a launch are dispatched to the 8 XCDs (each with its own L2)
+// in round-robin order.  This renumbering gives each XCD one contiguous range
+// of logical workgroup ids, so neighbouring data lands in one L2.
+struct XcdSlot {
+  uint32_t xcd;    // XCD this workgroup runs on
+  uint32_t index;  // its rank among that XCD's workgroups
+  uint32_t count;  // workgroups on that XCD
+};
+constexpr uint32_t kNumXcd = 8;
+__device__ __forceinline__ XcdSlot xcd_slot() {
+  const uint32_t n = gridDim.x, b = blockIdx.x;
+  XcdSlot s;
+  s.xcd = b % kNumXcd;
+  s.index = b / kNumXcd;
+  s.count = n / kNumXcd + (s.xcd < n % kNumXcd ? 1u : 0u);
+  return s;
+}
+__device__ __forceinline__ uint32_t xcd_block_id() {
+  const XcdSlot s = xcd_slot();
+  const uint32_t per = gridDim.x / kNumXcd, rem = gridDim.x % kNumXcd;
+  return s.xcd * per + (s.xcd < rem ? s.xcd : rem) + s.index;
+}
+
 // Launchers (one translation unit each); arguments already validated.
 ccl_status launch_init(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);

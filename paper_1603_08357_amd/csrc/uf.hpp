@@ -44,6 +44,23 @@ __device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
   return x;
 }
 
+// The same chase with path halving: every visited site is re-pointed at its
+// grandparent (a smaller member of the same cluster), so chains that many
+// concurrent joins stacked up shrink as threads walk them.  The plain store
+// may overwrite a value an atomicMin lowered meanwhile; that atomic's loop
+// re-joins the value it displaced, so no link is lost.
+__device__ __forceinline__ int32_t find_root_halving(int32_t* label, int32_t x) {
+  int32_t p = lab_ld(label + x);
+  while (p != x) {
+    const int32_t g = lab_ld(label + p);
+    if (g == p) return p;
+    lab_st(label + x, g);
+    x = g;
+    p = lab_ld(label + x);
+  }
+  return x;
+}
+
 // Join roots r1, r2 (any members work; roots save atomics): the label
 // reduction loop of Algorithm 1.  Order so that r1 > r2, then
 // old = atomicMin(label[r1], r2):
@@ -70,8 +87,8 @@ __device__ __forceinline__ void join_roots(int32_t* label, int32_t r1, int32_t r
 // Step (iii) for one bond (a, b): roots of both ends, then Algorithm 1.
 // Bonds whose ends already share a root issue no atomic.
 __device__ __forceinline__ void unite(int32_t* label, int32_t a, int32_t b) {
-  int32_t r1 = find_root(label, a);
-  int32_t r2 = find_root(label, b);
+  int32_t r1 = find_root_halving(label, a);
+  int32_t r2 = find_root_halving(label, b);
   if (r1 != r2) join_roots(label, r1, r2);
 }
 

@@ -46,6 +46,10 @@ class Job:
     t_admit: float = float("nan")
     t_done: float = float("nan")
     labels: np.ndarray | None = None
+    # optional pinned host copies of (src, dst, occ) for asynchronous uploads
+    pinned: tuple | None = None
+    # ids already checked (e.g. graphs from a validated pool): skip the O(B) scan
+    validated: bool = False
 
     @property
     def n_bonds(self) -> int:
@@ -73,7 +77,7 @@ def check_request(job: Job) -> str:
         return "occ must be uint8"
     if len(job.src) and job.n_sites == 0:
         return "bonds on an empty graph"
-    if len(job.src):
+    if len(job.src) and not job.validated:
         lo = min(int(job.src.min()), int(job.dst.min()))
         hi = max(int(job.src.max()), int(job.dst.max()))
         if lo < 0 or hi >= job.n_sites:
@@ -178,12 +182,13 @@ class GpuExecutor:
         pin = self.pinned.pop()
         with torch.cuda.stream(s):
             def h2d(a):
-                t = torch.from_numpy(a)
+                t = a if isinstance(a, torch.Tensor) else torch.from_numpy(a)
                 if not t.is_pinned():
                     t = t.pin_memory()
                 return t.to(self.device, non_blocking=True)
-            src, dst = h2d(job.src), h2d(job.dst)
-            occ = h2d(job.occ) if job.occ is not None else None
+            hs, hd, ho = job.pinned if job.pinned is not None else (job.src, job.dst, job.occ)
+            src, dst = h2d(hs), h2d(hd)
+            occ = h2d(ho) if ho is not None else None
             out = torch.empty(job.n_sites, dtype=torch.int32, device=self.device)
             self.ccl.label(src, dst, job.n_sites, occ, out=out, stream=s)
             host = pin[:job.n_sites]

@@ -323,3 +323,54 @@ def test_argument_errors(ccl):
     with pytest.raises(ccl.CclError):  # workspace too small for 40000 sites
         ccl.label_csr(dev(g.row_ptr), dev(g.col), dev(g.occ),
                       workspace=torch.empty(8, dtype=torch.uint8, device="cuda"))
+
+
+# ------------------------------------------------------------ serving & autotune
+
+def test_serving_mixed_equals_alone(ccl):
+    """Requests of mixed sizes served concurrently give each request the
+    labels it gets alone, and those equal the oracle's."""
+    from paper_1603_08357_amd.serving import GpuExecutor, Job, Scheduler
+
+    reqs = gen.request_trace(40, rate=2000.0, base_seed=17, n_max=200_000)
+    jobs = []
+    for r in reqs:
+        g = gen.request_graph(r)
+        jobs.append(Job(r.rid, r.arrival, g.n_sites, g.src, g.dst, g.occ))
+    bad = Job(999, jobs[5].arrival, 10, np.array([0, 11], np.int32), np.array([1, 2], np.int32),
+              np.ones(2, np.uint8))
+    jobs.insert(6, bad)
+    ex = GpuExecutor(n_streams=4, max_sites=max(j.n_sites for j in jobs))
+    budget = 3 * max(j.bytes for j in jobs if j is not bad)
+    sch = Scheduler(ex, budget, max_slots=4)
+    _say(f"serving {len(jobs)} requests")
+    done = sch.serve(jobs)
+    assert len(done) == len(jobs)
+    assert bad.status == "rejected"
+    assert sch.peak_used <= budget and sch.peak_running > 1
+    for j in jobs:
+        if j is bad:
+            continue
+        assert j.status == "done"
+        alone = gpu_edges(ccl, j.n_sites, j.src, j.dst, j.occ)
+        np.testing.assert_array_equal(j.labels, alone)
+        np.testing.assert_array_equal(j.labels, oracle.label_edges(j.n_sites, j.src, j.dst, j.occ))
+
+
+def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
+    from paper_1603_08357_amd import autotune
+    monkeypatch.setenv("CCL_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    specs = gen.batch_specs(64, base_seed=8, ls=(16, 64, 128, 256))
+    site_off, bond_off, src, dst, occ = _batch(specs)
+    want = oracle.label_batched(site_off, bond_off, src, dst, occ)
+    space = {"block_threads": (256, 512), "blocks_per_cu": (2, 4), "bonds_per_chunk": (16384,),
+             "sites_per_chunk": (16384,), "small_sites": (0, -1), "schedule": (2, 1)}
+    _say("autotune 16 candidates")
+    best = autotune.tune(site_off, bond_off, dev(src), dev(dst), dev(occ), space=space, reps=2)
+    assert (tmp_path / "cache.json").exists()
+    again = autotune.tune(site_off, bond_off, dev(src), dev(dst), dev(occ), space=space)
+    assert again == best  # served from the cache
+    plan = ccl.Plan(site_off, bond_off, best)
+    out = plan.label(dev(src), dev(dst), dev(occ))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), want)

@@ -146,3 +146,15 @@ def test_serve_replays_arrivals_with_fake_clock():
     assert len(done) == 50 and all(j.status == "done" for j in done)
     assert all(j.t_done >= j.arrival for j in done)
     assert all(j.t_admit >= j.arrival for j in done)
+
+
+def test_autotune_candidates_and_layout_key():
+    from paper_1603_08357_amd import autotune
+    c = autotune.candidates()
+    assert len(c) > 20
+    assert all(max(t["small_sites"], 0) * 4 * t["blocks_per_cu"] <= 160 * 1024 for t in c)
+    assert {t["schedule"] for t in c} == {1, 2}
+    k1 = autotune.layout_key([0, 100, 300, 1300])
+    k2 = autotune.layout_key([0, 110, 320, 1270])  # sizes 110, 210, 950
+    assert k1 == k2 and k1.startswith("K3-")
+    assert autotune.layout_key([0]) == "empty"
