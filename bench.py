@@ -95,6 +95,52 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 1 << 30  # the copy probe reads and writes this much
+KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
+                "k_flatten": "ccl_flatten", "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, workload: str) -> dict:
+    """Measured HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, KiB per dispatch) of
+        bench.py --steps 3 --warmup 1 --no-cpu-baseline --extras none --probe-copy
+    each scaled by what the counter reads for the copy probe (known bytes),
+    stored in profiles/traffic.json with the kernel-source hash."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name", counter) != counter:
+                    continue
+                name = row["Kernel_Name"].split("(")[0].split("<")[0].replace("ccl::", "")
+                vals[name].append(float(row["Counter_Value"]) * 1024.0)
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale = COPY_PROBE_BYTES / fetch["k_probe_copy"]
+    w_scale = COPY_PROBE_BYTES / write["k_probe_copy"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    rec = data.setdefault(workload, {})
+    for k, pub in KERNEL_NAMES.items():
+        if k in fetch and k in write:
+            rec[pub] = {"fetch_bytes": round(fetch[k] * f_scale), "write_bytes": round(write[k] * w_scale),
+                        "bytes_per_launch": round(fetch[k] * f_scale + write[k] * w_scale),
+                        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+                        "source_hash": kernel_source_hash()}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    return rec
+
+
 # ---------------------------------------------------------------- timing
 
 def time_steps(fn, steps: int, warmup: int, stream):
@@ -400,9 +446,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", choices=["all", "none"], default="all")
     ap.add_argument("--batch", type=int, default=4096, help="instances in the batched workload")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run the 1 GiB copy probe (counter calibration) when --extras none")
     ap.add_argument("--pool", type=int, default=24, help="graphs in the serving pool")
     ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="store measured traffic from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters, f"triangle-csr L={args.L} p={args.p}"),
+                         indent=1))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the labeling kernels run on a single MI355X "
@@ -441,6 +495,8 @@ def main():
         extra["labels_match_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
     del g
 
+    if args.extras == "none" and args.probe_copy:
+        extra["probe_copy"] = probe_copy()
     if args.extras == "all":
         try:
             extra["probe_copy"] = probe_copy()

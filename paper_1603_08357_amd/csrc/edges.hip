@@ -26,23 +26,59 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ label, in
   for (int64_t i = done + tid; i < n; i += stride) label[i] = (int32_t)i;
 }
 
-// Step (iii), one thread per bond: roots of both ends, then the atomicMin
-// loop of Algorithm 1.  Unoccupied bonds and same-root bonds issue nothing.
+// Step (iii): roots of both ends of every occupied bond, then the atomicMin
+// loop of Algorithm 1; unoccupied and same-root bonds issue nothing.  VEC:
+// src/dst are 16-byte aligned and a lane takes four consecutive bonds with
+// 16-byte loads (occ 4-byte aligned: one 4-byte load), then requests the first parent of
+// all eight ends before chasing any of them.
+template <bool VEC, bool HAS_OCC>
 __global__ void __launch_bounds__(kBlock)
     k_merge_edges(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                   const uint8_t* __restrict__ occ, int64_t m, int32_t* label) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < m; b += stride) {
-    if (occ != nullptr && occ[b] == 0) continue;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t done = 0;
+  if (VEC) {
+    const int64_t m4 = m >> 2;
+    for (int64_t q = tid; q < m4; q += stride) {
+      const int4 u4 = reinterpret_cast<const int4*>(src)[q];
+      const int4 v4 = reinterpret_cast<const int4*>(dst)[q];
+      uint32_t o4 = 0x01010101u;
+      if (HAS_OCC) o4 = reinterpret_cast<const uint32_t*>(occ)[q];  // byte j = bond 4q + j
+      const int32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+      const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+      int32_t pu[4], pv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool on = (o4 >> (8 * j)) & 0xFFu;
+        pu[j] = on ? lab_ld(label + u[j]) : u[j];
+        pv[j] = on ? lab_ld(label + v[j]) : v[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (((o4 >> (8 * j)) & 0xFFu) == 0) continue;
+        const int32_t r1 = find_root_halving_from(label, u[j], pu[j]);
+        const int32_t r2 = find_root_halving_from(label, v[j], pv[j]);
+        if (r1 != r2) join_roots(label, r1, r2);
+      }
+    }
+    done = m4 << 2;
+  }
+  for (int64_t b = done + tid; b < m; b += stride) {
+    if (HAS_OCC && occ[b] == 0) continue;
     unite(label, src[b], dst[b]);
   }
 }
 
 // Step (iv): every site follows its label to the root and stores it, four
-// sites per lane (16-byte loads and stores when aligned), with path halving
-// on the chase.  Workgroups own contiguous site ranges, renumbered so that
-// each XCD's L2 holds one region of the array.  Other threads may read or
-// halve a label meanwhile; every value stored is a valid link.
+// sites per lane (16-byte loads and stores when aligned).  Workgroups own
+// contiguous site ranges, renumbered so that each XCD's L2 holds one region
+// of the array.  Every store in this step is a root: the owner of a site
+// stores its root, and a chase that started at a site's parent p also stores
+// the root into p, so the many sites sharing p find it in one step.  Both are
+// final values (every writer of p stores the same root), whereas a shortcut
+// to a non-root ancestor could land after the owner's final store and leave a
+// non-root label behind -- so the chase itself stores nothing else.
 template <bool VEC>
 __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
   const int64_t groups = (n + 3) >> 2;
@@ -61,7 +97,9 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
         if (p == (int32_t)(i0 + j)) continue;
         const int32_t q = lab_ld(label + p);
         if (q == p) continue;
-        c[j] = find_root_halving(label, q);
+        const int32_t r = find_root(label, q);
+        if (r != q) lab_st(label + p, r);
+        c[j] = r;
         changed = true;
       }
       if (changed) reinterpret_cast<int4*>(label)[g] = v;
@@ -70,7 +108,10 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
         const int32_t p = lab_ld(label + i);
         if (p == (int32_t)i) continue;
         const int32_t q = lab_ld(label + p);
-        if (q != p) lab_st(label + i, find_root_halving(label, q));
+        if (q == p) continue;
+        const int32_t r = find_root(label, q);
+        if (r != q) lab_st(label + p, r);
+        lab_st(label + i, r);
       }
     }
   }
@@ -102,9 +143,19 @@ ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const in
                               const DeviceInfo& d) {
   ccl_status st = launch_init(n, label, s, d);
   if (st != CCL_OK) return st;
-  if (m > 0)
-    CCL_LAUNCH("ccl_merge_edges", k_merge_edges, grid_for(m, kBlock, 8, d), kBlock, 0, s, src,
-               dst, occ, m, label);
+  if (m > 0) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(occ) & 3) == 0;
+    const unsigned g = grid_for(vec ? (m + 3) / 4 : m, kBlock, 8, d);
+    if (vec && occ)
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, true>), g, kBlock, 0, s, src, dst, occ, m, label);
+    else if (vec)
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, false>), g, kBlock, 0, s, src, dst, occ, m, label);
+    else if (occ)
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, true>), g, kBlock, 0, s, src, dst, occ, m, label);
+    else
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, false>), g, kBlock, 0, s, src, dst, occ, m, label);
+  }
   return launch_flatten(n, label, s, d);
 }
 
@@ -132,13 +183,24 @@ ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const
 
 // ---------------------------------------------------------------- probe
 
-// Streaming copy, 16 bytes per lane per iteration; the tail byte by byte.
+// Streaming copy: four 16-byte loads per lane in flight before the four
+// stores, workgroups on contiguous XCD-local ranges; the tail byte by byte.
 __global__ void __launch_bounds__(kBlock)
     k_probe_copy(const int4* __restrict__ in, int4* __restrict__ out, int64_t n16,
                  const uint8_t* __restrict__ in_b, uint8_t* __restrict__ out_b, int64_t tail) {
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  constexpr int U = 4;
+  const int64_t per = (n16 + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)xcd_block_id() * per, hi = min(lo + per, n16);
+  int64_t i = lo + threadIdx.x;
+  for (; i + (U - 1) * kBlock < hi; i += U * kBlock) {
+    int4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = in[i + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < U; ++u) out[i + u * kBlock] = v[u];
+  }
+  for (; i < hi; i += kBlock) out[i] = in[i];
   const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  for (int64_t i = tid; i < n16; i += stride) out[i] = in[i];
   if (tid < tail) out_b[tid] = in_b[tid];
 }
 

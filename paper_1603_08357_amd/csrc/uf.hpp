@@ -48,9 +48,24 @@ __device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
 // grandparent (a smaller member of the same cluster), so chains that many
 // concurrent joins stacked up shrink as threads walk them.  The plain store
 // may overwrite a value an atomicMin lowered meanwhile; that atomic's loop
-// re-joins the value it displaced, so no link is lost.
+// re-joins the value it displaced, so no link is lost.  For the merge step
+// only: a halving store can also land after another thread wrote a site's
+// root, which the flatten step must never allow (its writes are final).
 __device__ __forceinline__ int32_t find_root_halving(int32_t* label, int32_t x) {
   int32_t p = lab_ld(label + x);
+  while (p != x) {
+    const int32_t g = lab_ld(label + p);
+    if (g == p) return p;
+    lab_st(label + x, g);
+    x = g;
+    p = lab_ld(label + x);
+  }
+  return x;
+}
+
+// find_root_halving for a chase whose first parent p = label[x] is already
+// loaded (lets a caller issue the first loads of several chases together).
+__device__ __forceinline__ int32_t find_root_halving_from(int32_t* label, int32_t x, int32_t p) {
   while (p != x) {
     const int32_t g = lab_ld(label + p);
     if (g == p) return p;
