@@ -43,10 +43,10 @@ def log(*a):
 # read / written once), independent of how many bytes the hardware moves.
 
 def alg_bytes_csr(kernel: str, n: int, m: int) -> float:
-    if kernel == "ccl_csr_tile":  # row_ptr + col + occ read, labels written, mask written
-        return 4.0 * (n + 1) + 5.0 * m + 4.0 * n + n / 8.0
-    if kernel == "ccl_csr_cross":  # the row mask
-        return n / 8.0
+    if kernel == "ccl_csr_tile":  # row_ptr + col + occ read, labels written
+        return 4.0 * (n + 1) + 5.0 * m + 4.0 * n
+    if kernel == "ccl_csr_cross":  # nothing the method itself must move
+        return 0.0
     if kernel == "ccl_flatten":  # labels read and written
         return 8.0 * n
     return 0.0
@@ -200,7 +200,7 @@ def bench_csr(L, p, seed, steps, warmup):
     col = torch.from_numpy(g.col).cuda()
     occ = torch.from_numpy(g.occ).cuda()
     out = torch.empty(n, dtype=torch.int32, device="cuda")
-    ws = torch.empty(max(ccl.csr_workspace_bytes(n), 8), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream)
     ms, wall = time_steps(fn, steps, warmup, stream)

@@ -69,10 +69,11 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
                      const uint8_t* occupied, int32_t* labels_out, void* stream);
 
 /*
- * Workspace bytes ccl_label_csr needs for n_sites sites (one bit per site,
- * rounded up to whole 64-bit words).
+ * Workspace bytes ccl_label_csr needs: zero for n_sites <= 32768 (one tile),
+ * else one 8-byte slot per bond (the bonds leaving their tile are collected
+ * there) plus 8 bytes per 32768-site tile, rounded up to 256 bytes.
  */
-size_t ccl_label_csr_workspace_size(int64_t n_sites);
+size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds);
 
 /*
  * Label the clusters of a graph in compressed-sparse-row form: row i holds the
@@ -80,21 +81,25 @@ size_t ccl_label_csr_workspace_size(int64_t n_sites);
  * needs to appear once (a "half" CSR such as forward neighbours only), but
  * listing it in both rows is also correct.  The paper's neighbour list
  * (section 3) is this structure with all neighbours listed.
- *   row_ptr    device int32[N+1], non-decreasing, row_ptr[N] < 2^31
- *   col        device int32[row_ptr[N]]
- *   occupied   device uint8[row_ptr[N]] aligned with col, or NULL
- *   workspace  device buffer of at least ccl_label_csr_workspace_size(N)
- *              bytes, 8-byte aligned; contents need not be initialised and are
- *              garbage afterwards.  May be NULL only when N <= 32768 (a single
- *              tile needs none).
- * Kernels: sites are cut into tiles of consecutive ids; one workgroup per tile
- * initialises its labels (step i) and joins the tile-internal bonds in LDS
- * (step iii on the tile), then the bonds that leave a tile are joined in
- * global memory (step iii, Algorithm 1) and the labels flattened (step iv).
+ *   n_sites    N (0 <= N <= INT32_MAX)
+ *   n_bonds    at least row_ptr[N] - row_ptr[0] (e.g. the length of col);
+ *              sizes the workspace, must not be smaller
+ *   row_ptr    device int32[N+1], non-decreasing, row_ptr[0] >= 0
+ *   col        device int32[], entries row_ptr[0] .. row_ptr[N]-1 are read
+ *   occupied   device uint8[], aligned with col, or NULL
+ *   workspace  device buffer of at least ccl_label_csr_workspace_size(N,
+ *              n_bonds) bytes, 8-byte aligned, contents need not be
+ *              initialised and are garbage afterwards; may be NULL when that
+ *              size is zero
+ * Kernels: sites are cut into tiles of 32768 consecutive ids; one workgroup
+ * per tile initialises its labels (step i) and joins the tile-internal bonds
+ * in LDS (step iii on the tile), recording the bonds that leave the tile in
+ * the workspace; then those bonds are joined in global memory (step iii,
+ * Algorithm 1) and the labels flattened (step iv).
  */
-ccl_status ccl_label_csr(int64_t n_sites, const int32_t* row_ptr, const int32_t* col,
-                         const uint8_t* occupied, int32_t* labels_out, void* workspace,
-                         size_t workspace_bytes, void* stream);
+ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                         const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
+                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batches */
 

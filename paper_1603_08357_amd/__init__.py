@@ -58,8 +58,8 @@ def _load():
     st = ctypes.c_int
     sig = {
         "ccl_label": (st, [i64, i64, P, P, P, P, P]),
-        "ccl_label_csr_workspace_size": (sz, [i64]),
-        "ccl_label_csr": (st, [i64, P, P, P, P, P, sz, P]),
+        "ccl_label_csr_workspace_size": (sz, [i64, i64]),
+        "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
         "ccl_plan_destroy": (st, [P]),
         "ccl_plan_get_tuning": (st, [P, P]),
@@ -133,31 +133,36 @@ def label(src: torch.Tensor, dst: torch.Tensor, n_sites: int, occ: torch.Tensor 
     return out
 
 
-def csr_workspace_bytes(n_sites: int) -> int:
-    return int(_lib.ccl_label_csr_workspace_size(n_sites))
+def csr_workspace_bytes(n_sites: int, n_bonds: int) -> int:
+    """Workspace ccl_label_csr needs (0 for a graph of one 32768-site tile)."""
+    return int(_lib.ccl_label_csr_workspace_size(n_sites, n_bonds))
 
 
 def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None = None,
               out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
               stream=None) -> torch.Tensor:
-    """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1.
-    `workspace` (uint8, >= csr_workspace_bytes(n) bytes) is allocated when None."""
+    """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1,
+    bonds row_ptr[0] .. row_ptr[n]-1 of col (len(col) bounds their count).
+    `workspace` (uint8, >= csr_workspace_bytes(n, len(col)) bytes) is
+    allocated when None."""
     dev = row_ptr.device
     n = row_ptr.numel() - 1
     if n < 0:
         raise ValueError("row_ptr must hold n_sites + 1 entries")
+    m = col.numel()
     prp = _dev_ptr(row_ptr, torch.int32, "row_ptr", None, dev)
     pc = _dev_ptr(col, torch.int32, "col", None, dev)
-    po = _dev_ptr(occ, torch.uint8, "occ", col.numel(), dev)
+    po = _dev_ptr(occ, torch.uint8, "occ", m, dev)
     if out is None:
         out = torch.empty(n, dtype=torch.int32, device=dev)
     pl = _dev_ptr(out, torch.int32, "out", n, dev)
-    need = csr_workspace_bytes(n)
-    if workspace is None:
-        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=dev)
+    need = csr_workspace_bytes(n, m)
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     pw = _dev_ptr(workspace, torch.uint8, "workspace", None, dev)
+    wbytes = workspace.numel() if workspace is not None else 0
     with torch.cuda.device(dev):
-        _check(_lib.ccl_label_csr(n, prp, pc, po, pl, pw, workspace.numel(), _stream(stream, dev)),
+        _check(_lib.ccl_label_csr(n, m, prp, pc, po, pl, pw, wbytes, _stream(stream, dev)),
                "ccl_label_csr")
     return out
 

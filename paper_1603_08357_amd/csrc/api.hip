@@ -126,31 +126,32 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
                             *d);
 }
 
-size_t ccl_label_csr_workspace_size(int64_t n_sites) {
-  if (n_sites <= 0) return 0;
-  return (size_t)((n_sites + 63) / 64) * sizeof(uint64_t);
+size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds) {
+  if (n_sites <= 0 || n_bonds < 0) return 0;
+  return csr_workspace_bytes(n_sites, n_bonds);
 }
 
-ccl_status ccl_label_csr(int64_t n_sites, const int32_t* row_ptr, const int32_t* col,
-                         const uint8_t* occupied, int32_t* labels_out, void* workspace,
-                         size_t workspace_bytes, void* stream) {
-  if (n_sites < 0 || n_sites > INT32_MAX) return CCL_ERR_INVALID_VALUE;
+ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                         const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX || n_bonds < 0 || n_bonds > INT32_MAX)
+    return CCL_ERR_INVALID_VALUE;
   if (n_sites == 0) return CCL_OK;
-  if (row_ptr == nullptr || col == nullptr || labels_out == nullptr) return CCL_ERR_INVALID_VALUE;
-  if (n_sites > kCsrTile) {
-    if (workspace == nullptr || workspace_bytes < ccl_label_csr_workspace_size(n_sites) ||
-        ((uintptr_t)workspace & 7) != 0)
-      return CCL_ERR_INVALID_VALUE;
-  }
+  if (row_ptr == nullptr || labels_out == nullptr || (n_bonds > 0 && col == nullptr))
+    return CCL_ERR_INVALID_VALUE;
+  const size_t need = ccl_label_csr_workspace_size(n_sites, n_bonds);
+  if (need > 0 && (workspace == nullptr || workspace_bytes < need || ((uintptr_t)workspace & 7) != 0))
+    return CCL_ERR_INVALID_VALUE;
   const size_t lb = (size_t)n_sites * 4;
-  if (overlaps(labels_out, lb, row_ptr, lb + 4) ||
-      overlaps(labels_out, lb, workspace, workspace ? workspace_bytes : 0))
+  if (overlaps(labels_out, lb, row_ptr, lb + 4) || overlaps(labels_out, lb, col, (size_t)n_bonds * 4) ||
+      overlaps(labels_out, lb, occupied, (size_t)n_bonds) ||
+      overlaps(labels_out, lb, workspace, need))
     return CCL_ERR_INVALID_VALUE;
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
-  return launch_label_csr(n_sites, row_ptr, col, occupied, labels_out,
-                          static_cast<uint64_t*>(workspace), (hipStream_t)stream, *d);
+  return launch_label_csr(n_sites, row_ptr, col, occupied, labels_out, need ? workspace : nullptr,
+                          (hipStream_t)stream, *d);
 }
 
 static ccl_status run_count(unsigned long long* n_bad, hipStream_t s,

@@ -89,11 +89,33 @@ __device__ __forceinline__ int32_t find_root_checked(const int32_t* lab, int32_t
   return x;
 }
 
+// The merge step's chase: path halving (see find_root_halving), with the
+// same refusal of labels that point upward or below zero.
+__device__ __forceinline__ int32_t find_root_halving_checked(int32_t* lab, int32_t x, bool& bad) {
+  int32_t p = lab_ld(lab + x);
+  while (p != x) {
+    if (p > x || p < 0) {
+      bad = true;
+      return x;
+    }
+    const int32_t g = lab_ld(lab + p);
+    if (g == p) return p;
+    if (g > p || g < 0) {
+      bad = true;
+      return x;
+    }
+    lab_st(lab + x, g);
+    x = g;
+    p = lab_ld(lab + x);
+  }
+  return x;
+}
+
 // Algorithm 1 with the same refusal: a returned old value above r1 or below
 // zero cannot come from a valid forest.
 __device__ __forceinline__ void unite_checked(int32_t* lab, int32_t a, int32_t b, bool& bad) {
-  int32_t r1 = find_root_checked(lab, a, bad);
-  int32_t r2 = find_root_checked(lab, b, bad);
+  int32_t r1 = find_root_halving_checked(lab, a, bad);
+  int32_t r2 = find_root_halving_checked(lab, b, bad);
   while (!bad && r1 != r2) {
     if (r1 < r2) {
       int32_t t = r1;
@@ -204,6 +226,8 @@ __global__ void k_batched(BatchArgs a) {
       if (go) {
         const int32_t lo = c * a.sites_per_chunk;
         const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
+        // only roots are stored (see the flatten of the single-instance
+        // path): the site's own root, and the root into the site's parent
         for (int32_t i = lo + threadIdx.x; i < hi && !bad; i += blockDim.x) {
           const int32_t p = lab_ld(lab + i);
           if (p == i) continue;
@@ -211,8 +235,12 @@ __global__ void k_batched(BatchArgs a) {
             bad = true;
             break;
           }
-          const int32_t r = find_root_checked(lab, p, bad);
-          if (!bad && r != p) lab_st(lab + i, r);
+          const int32_t q = lab_ld(lab + p);
+          if (q == p) continue;
+          const int32_t r = find_root_checked(lab, q, bad);
+          if (bad) break;
+          if (r != q) lab_st(lab + p, r);
+          lab_st(lab + i, r);
         }
       }
     }

@@ -6,10 +6,12 @@
 //      (par[t] = t), step (iii) -- Algorithm 1 on LDS with ds_min -- for every
 //      occupied bond whose two ends lie in the tile, a root chase in LDS, and
 //      one coalesced store of the tile's labels (each site's tile-local root,
-//      the tile's minimum member of its local cluster).  Rows holding an
-//      occupied bond that leaves the tile are flagged in a bit mask;
+//      the tile's minimum member of its local cluster).  Occupied bonds that
+//      leave the tile are appended, as (site, neighbour) pairs, to the tile's
+//      own segment of the workspace (the segment has room for every bond of
+//      the tile, so no global counter is needed);
 //   2. cross kernel: step (iii) in global memory (Algorithm 1 with
-//      device-scope atomicMin) for the occupied leaving bonds of flagged rows;
+//      device-scope atomicMin) over those pairs;
 //   3. flatten: step (iv).
 // Every value the tile kernel stores is a member of the site's cluster no
 // larger than the site, so kernels 2-3 see a valid forest and finish the job
@@ -21,8 +23,9 @@ namespace ccl {
 
 constexpr int kTileBlock = 1024;
 constexpr int kTileShift = 15;
-constexpr int kRowsPerThread = 4;  // rows a thread handles per iteration
-constexpr int kDegFast = 4;        // bonds per row kept in registers; more take a slow loop
+constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
+constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
+constexpr int kChunkRows = kTileBlock * kRowsPerThread;
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
 // Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
@@ -37,39 +40,83 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 __device__ __forceinline__ int32_t buf_i32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
 }
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
+}
 __device__ __forceinline__ uint32_t buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
   return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)byte_off, 0, 0);
 }
+__device__ __forceinline__ int4 buf_i32x4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
+  return make_int4((int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]);
+}
 
-// One workgroup per tile.  Each iteration covers kTileBlock * kRowsPerThread
-// rows (row base + k * kTileBlock + tid for k < kRowsPerThread, so every load
-// instruction is coalesced across the wave); the next iteration's row_ptr
-// values are requested before this iteration's joins run, and the first
-// kDegFast bonds of every row are requested in one batch of buffer loads, so
-// a wave keeps dozens of loads in flight instead of waiting on each row.
-// The buffer resources are based at the tile's first row and first bond, so
-// offsets stay small whatever the graph size (a tile holding 2^30 or more
-// bonds takes the plain-load loop instead).
+// Tile-relative row of tile-relative bond e in an affine tile of degree d.
+__device__ __forceinline__ int32_t affine_row(int32_t e, int32_t d) {
+  switch (d) {
+    case 1: return e;
+    case 2: return e >> 1;
+    case 3: return e / 3;
+    default: return e >> 2;
+  }
+}
+
+// Join bond (t, v) of the tile (t tile-relative, v global) or record it as
+// leaving: `pairs` is the tile's segment, `n_out` the LDS slot counter.
+__device__ __forceinline__ void tile_bond(int32_t* par, int32_t t, int32_t v, int64_t lo,
+                                          int32_t cnt, int2* pairs, uint32_t* n_out) {
+  const int64_t vl = (int64_t)v - lo;
+  if (vl >= 0 && vl < cnt) {
+    lds_unite(par, t, (int32_t)vl);
+  } else {
+    const uint32_t slot =
+        __hip_atomic_fetch_add(n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    pairs[slot] = make_int2((int32_t)(lo + t), v);
+  }
+}
+
+// One workgroup per tile.
+// Affine path (the tile's row_ptr is e_begin + d*r with 1 <= d <= 4, checked
+// row by row from the same loads): each iteration takes kChunkRows rows and
+// their d*kChunkRows bonds; lane tid loads bonds 4q..4q+3 (q = j*kTileBlock +
+// tid, j < d) with one 16-byte col load and one 4-byte occ load, so every
+// load instruction is a fully coalesced vector load.
+// Row path (any other CSR): kRowsPerThread rows per lane, the first kDegFast
+// bonds of each row in one batch of buffer loads, longer rows in a loop.
+// Either way the next iteration's row_ptr loads are issued before this one's
+// joins.  Buffer resources are based at the tile's first row and first bond,
+// so offsets stay small whatever the graph size; a tile with 2^30 or more
+// bonds uses plain loads.
 template <bool HAS_OCC>
 __global__ void __launch_bounds__(kTileBlock)
     k_csr_tile(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
-               uint64_t* __restrict__ rowmask) {
+               int2* __restrict__ pairs, int2* __restrict__ seg) {
   __shared__ int32_t par[kCsrTile];
+  __shared__ uint32_t n_out;
   const int64_t lo = (int64_t)blockIdx.x << kTileShift;
   const int32_t cnt = (int32_t)min((int64_t)kCsrTile, n - lo);
-  const int tid = threadIdx.x, lane = tid & 63;
-  constexpr int kRows = kTileBlock * kRowsPerThread;
+  const int tid = threadIdx.x;
+  const int32_t e0 = row_ptr[0];
   const int32_t e_begin = row_ptr[lo];
   const int32_t e_count = row_ptr[lo + cnt] - e_begin;
-  const bool fast = e_count < (1 << 30);
+  const bool fast = e_count >= 0 && e_count < (1 << 30);
+  // the tile's segment of the pair list: one slot per bond of the tile
+  int2* my_pairs = pairs != nullptr ? pairs + (e_begin - e0) : nullptr;
+  const int32_t deg = (fast && cnt > 0 && e_count % cnt == 0) ? e_count / cnt : 0;
+  const bool affine_try =
+      deg >= 1 && deg <= 4 &&
+      (!HAS_OCC || ((reinterpret_cast<uintptr_t>(occ + e_begin) & 3) == 0));
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(row_ptr + lo, (uint32_t)(cnt + 1) * 4u);
   const __amdgpu_buffer_rsrc_t rc = make_rsrc(col + e_begin, fast ? (uint32_t)e_count * 4u : 0u);
   const __amdgpu_buffer_rsrc_t ro =
       make_rsrc(HAS_OCC ? occ + e_begin : nullptr, fast && HAS_OCC ? (uint32_t)e_count : 0u);
 
-  // row t's bonds are [ra, rb) relative to e_begin; rows past the tile read
-  // 0 (or the end value) and so hold no bonds
+  for (int t = tid; t < kCsrTile; t += kTileBlock) par[t] = t;
+  if (tid == 0) n_out = 0;
+
+  // row_ptr of this lane's rows in the first chunk (relative to e_begin);
+  // rows past the tile read 0 or the end value and so hold no bonds
   int32_t ra[kRowsPerThread], rb[kRowsPerThread];
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
@@ -77,117 +124,163 @@ __global__ void __launch_bounds__(kTileBlock)
     ra[k] = buf_i32(rp, 4u * t) - e_begin;
     rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
   }
-  for (int t = tid; t < kCsrTile; t += kTileBlock) par[t] = t;
   __syncthreads();
 
-  for (int base = 0; base < cnt; base += kRows) {
-    int32_t cv[kRowsPerThread][kDegFast];
-    uint32_t ov[kRowsPerThread][kDegFast];
-#pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k)
-#pragma unroll
-      for (int j = 0; j < kDegFast; ++j) {
-        const int32_t e = ra[k] + j;
-        const uint32_t off = (fast && e < rb[k] && base + k * kTileBlock + tid < cnt)
-                                 ? (uint32_t)e : kOffNone;
-        cv[k][j] = buf_i32(rc, off * 4u);
-        ov[k][j] = HAS_OCC ? buf_u8(ro, off) : (off != kOffNone ? 1u : 0u);
-      }
-    int32_t na[kRowsPerThread], nb[kRowsPerThread];
+  bool affine = affine_try;
+  for (int base = 0; base < cnt; base += kChunkRows) {
+    // is this chunk affine?  (every lane checks its rows; one vote)
+    bool ok = true;
 #pragma unroll
     for (int k = 0; k < kRowsPerThread; ++k) {
-      const uint32_t t = (uint32_t)(base + kRows + k * kTileBlock + tid);
-      na[k] = buf_i32(rp, 4u * t) - e_begin;
-      nb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
+      const int32_t t = base + k * kTileBlock + tid;
+      if (t < cnt) ok = ok && ra[k] == deg * t && rb[k] == deg * (t + 1);
     }
+    affine = __syncthreads_and(affine && ok) != 0;
+
+    if (affine) {
+      const int32_t cb = deg * base;                                     // chunk's first bond
+      const int32_t ce = deg * (int32_t)min(base + kChunkRows, (int)cnt);  // one past its last
+      int4 cv[4];
+      uint32_t ov[4];
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      const int t = base + k * kTileBlock + tid;
-      bool leaves = false;
-      if (t < cnt) {
+      for (int j = 0; j < 4; ++j) {
+        // whole groups of four bonds only: the (at most one) group that
+        // straddles the end of the tile is read below with plain loads
+        const int32_t e = cb + 4 * (j * kTileBlock + tid);
+        const uint32_t off = (j < deg && e + 4 <= ce) ? (uint32_t)e : kOffNone;
+        cv[j] = buf_i32x4(rc, off * 4u);
+        ov[j] = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
+      }
+      // next chunk's row_ptr for its check
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const uint32_t t = (uint32_t)(base + kChunkRows + k * kTileBlock + tid);
+        ra[k] = buf_i32(rp, 4u * t) - e_begin;
+        rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t e = cb + 4 * (j * kTileBlock + tid);
+        const int32_t c4[4] = {cv[j].x, cv[j].y, cv[j].z, cv[j].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (((ov[j] >> (8 * c)) & 0xFFu) == 0) continue;
+          tile_bond(par, affine_row(e + c, deg), c4[c], lo, cnt, my_pairs, &n_out);
+        }
+        if (j < deg && e < ce && e + 4 > ce) {
+          for (int32_t x = e; x < ce; ++x) {
+            const int64_t ge = (int64_t)e_begin + x;
+            if (HAS_OCC && occ[ge] == 0) continue;
+            tile_bond(par, affine_row(x, deg), col[ge], lo, cnt, my_pairs, &n_out);
+          }
+        }
+      }
+    } else {
+      int32_t cv[kRowsPerThread][kDegFast];
+      uint32_t ov[kRowsPerThread][kDegFast];
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k)
 #pragma unroll
         for (int j = 0; j < kDegFast; ++j) {
-          if (ov[k][j] == 0) continue;
-          const int64_t v = (int64_t)cv[k][j] - lo;
-          if (v >= 0 && v < cnt)
-            lds_unite(par, t, (int32_t)v);
-          else
-            leaves = true;
+          const int32_t e = ra[k] + j;
+          const uint32_t off =
+              (fast && e < rb[k] && base + k * kTileBlock + tid < cnt) ? (uint32_t)e : kOffNone;
+          cv[k][j] = buf_i32(rc, off * 4u);
+          ov[k][j] = HAS_OCC ? buf_u8(ro, off) : (off != kOffNone ? 1u : 0u);
         }
+      int32_t na[kRowsPerThread], nb[kRowsPerThread];
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const uint32_t t = (uint32_t)(base + kChunkRows + k * kTileBlock + tid);
+        na[k] = buf_i32(rp, 4u * t) - e_begin;
+        nb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
+      }
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int t = base + k * kTileBlock + tid;
+        if (t >= cnt) continue;
+#pragma unroll
+        for (int j = 0; j < kDegFast; ++j)
+          if (ov[k][j] != 0) tile_bond(par, t, cv[k][j], lo, cnt, my_pairs, &n_out);
         for (int32_t e = ra[k] + (fast ? kDegFast : 0); e < rb[k]; ++e) {
           const int64_t ge = (int64_t)e_begin + e;
           if (HAS_OCC && occ[ge] == 0) continue;
-          const int64_t v = (int64_t)col[ge] - lo;
-          if (v >= 0 && v < cnt)
-            lds_unite(par, t, (int32_t)v);
-          else
-            leaves = true;
+          tile_bond(par, t, col[ge], lo, cnt, my_pairs, &n_out);
         }
       }
-      const uint64_t bits = __ballot(leaves);
-      const int wave_first = base + k * kTileBlock + (tid & ~63);
-      if (lane == 0 && wave_first < cnt && rowmask != nullptr)
-        rowmask[(lo + wave_first) >> 6] = bits;
-    }
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      ra[k] = na[k];
-      rb[k] = nb[k];
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        ra[k] = na[k];
+        rb[k] = nb[k];
+      }
     }
   }
   __syncthreads();
   for (int t = tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds_find(par, t));
+  if (tid == 0 && seg != nullptr) seg[blockIdx.x] = make_int2(e_begin - e0, (int32_t)n_out);
 }
 
-// Cross kernel: the 64-row mask words are split into 8 contiguous ranges, one
-// per XCD, so the tiles a range joins stay in one L2; inside a range the
-// XCD's wavefronts take words round-robin.  Lane j of the wave owns row
-// 64w + j and joins that row's occupied bonds leaving its tile.
+// Cross kernel: one workgroup per tile (tiles renumbered so that each XCD
+// takes a contiguous range of them and its L2 holds the neighbouring tiles
+// those joins touch).  Lanes take four leaving bonds at a time, request the
+// first parent of all eight ends together, then chase and join.
 __global__ void __launch_bounds__(256)
-    k_csr_cross(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                const uint8_t* __restrict__ occ, int32_t* label,
-                const uint64_t* __restrict__ rowmask, int64_t n_words) {
-  const int lane = threadIdx.x & 63;
-  const XcdSlot x = xcd_slot();
-  const int64_t w_lo = n_words * x.xcd / kNumXcd;
-  const int64_t w_hi = n_words * (x.xcd + 1) / kNumXcd;
-  const int64_t waves = (int64_t)x.count * (256 / 64);
-  const int64_t me = (int64_t)x.index * (256 / 64) + (threadIdx.x >> 6);
-  for (int64_t w = w_lo + me; w < w_hi; w += waves) {
-    const uint64_t bits = rowmask[w];
-    if (((bits >> lane) & 1ull) == 0) continue;
-    const int64_t r = (w << 6) + lane;
-    const int64_t tlo = (r >> kTileShift) << kTileShift;
-    const int64_t thi = min(tlo + kCsrTile, n);
-    const int32_t e1 = row_ptr[r + 1];
-    for (int32_t e = row_ptr[r]; e < e1; ++e) {
-      if (occ != nullptr && occ[e] == 0) continue;
-      const int32_t v = col[e];
-      if (v < tlo || v >= thi) unite(label, (int32_t)r, v);
+    k_csr_cross(const int2* __restrict__ pairs, const int2* __restrict__ seg, int32_t* label) {
+  const uint32_t tile = xcd_block_id();
+  const int2 sc = seg[tile];
+  const int2* p = pairs + sc.x;
+  const int32_t count = sc.y;
+  for (int32_t i = 4 * threadIdx.x; i < count; i += 4 * 256) {
+    int32_t u[4], v[4], pu[4], pv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int2 e = i + k < count ? p[i + k] : make_int2(0, 0);
+      u[k] = e.x;
+      v[k] = e.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool in = i + k < count;
+      pu[k] = in ? lab_ld(label + u[k]) : u[k];
+      pv[k] = in ? lab_ld(label + v[k]) : v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k >= count) continue;
+      const int32_t r1 = find_root_halving_from(label, u[k], pu[k]);
+      const int32_t r2 = find_root_halving_from(label, v[k], pv[k]);
+      if (r1 != r2) join_roots(label, r1, r2);
     }
   }
 }
 
+size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds) {
+  if (n_sites <= kCsrTile) return 0;
+  const int64_t n_tiles = (n_sites + kCsrTile - 1) / kCsrTile;
+  const size_t seg = ((size_t)n_tiles * sizeof(int2) + 255) & ~(size_t)255;
+  return seg + (size_t)n_bonds * sizeof(int2);
+}
+
 ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
-                            const uint8_t* occ, int32_t* label, uint64_t* rowmask,
+                            const uint8_t* occ, int32_t* label, void* workspace,
                             hipStream_t s, const DeviceInfo& d) {
   if (n == 0) return CCL_OK;
   const int64_t n_tiles = (n + kCsrTile - 1) / kCsrTile;
-  // a single tile has no leaving bonds to record: the mask is not touched
-  uint64_t* mask = n_tiles == 1 ? nullptr : rowmask;
+  int2* seg = nullptr;
+  int2* pairs = nullptr;
+  if (n_tiles > 1) {  // a single tile has no leaving bonds and needs no workspace
+    seg = static_cast<int2*>(workspace);
+    pairs = reinterpret_cast<int2*>(static_cast<char*>(workspace) +
+                                    (((size_t)n_tiles * sizeof(int2) + 255) & ~(size_t)255));
+  }
   if (occ != nullptr)
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<true>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
-               col, occ, label, mask);
+               col, occ, label, pairs, seg);
   else
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<false>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
-               col, occ, label, mask);
-  if (n_tiles == 1) return CCL_OK;  // no bond can leave the only tile
-  const int64_t n_words = (n + 63) >> 6;
-  // every XCD needs workgroups: each one owns a range of the mask words
-  unsigned g = grid_for(n_words * 64, 256, 8, d);
-  g = (g + kNumXcd - 1) / kNumXcd * kNumXcd;
-  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, g, 256, 0, s, n, row_ptr, col, occ, label, rowmask,
-             n_words);
+               col, occ, label, pairs, seg);
+  if (n_tiles == 1) return CCL_OK;
+  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, 256, 0, s, pairs, seg, label);
   return launch_flatten(n, label, s, d);
 }
 

@@ -90,15 +90,18 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
     if (VEC && i0 + 3 < n) {
       int4 v = reinterpret_cast<const int4*>(label)[g];
       int32_t* c = reinterpret_cast<int32_t*>(&v);
+      // the four parents' labels, requested together (every label is a
+      // valid index, so the loads need no guard)
+      int32_t q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) q[j] = lab_ld(label + c[j]);
       bool changed = false;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int32_t p = c[j];
-        if (p == (int32_t)(i0 + j)) continue;
-        const int32_t q = lab_ld(label + p);
-        if (q == p) continue;
-        const int32_t r = find_root(label, q);
-        if (r != q) lab_st(label + p, r);
+        if (p == (int32_t)(i0 + j) || q[j] == p) continue;
+        const int32_t r = find_root(label, q[j]);
+        if (r != q[j]) lab_st(label + p, r);
         c[j] = r;
         changed = true;
       }

@@ -73,15 +73,19 @@ def test_host_side_argument_errors(lib):
     assert lib.ccl_label(10, 10, ctypes.c_void_p(4096), ctypes.c_void_p(8192), None,
                          ctypes.c_void_p(4096 + 8), None) == INVALID
     # CSR: > one tile needs a workspace of the right size and alignment
-    n = 100_000
-    assert lib.ccl_label_csr_workspace_size(n) == ((n + 63) // 64) * 8
-    assert lib.ccl_label_csr_workspace_size(0) == 0
-    args = (n, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), None, ctypes.c_void_p(1 << 28))
+    n, m = 100_000, 300_000
+    n_tiles = (n + 32767) // 32768
+    assert lib.ccl_label_csr_workspace_size(n, m) == (n_tiles * 8 + 255) // 256 * 256 + 8 * m
+    assert lib.ccl_label_csr_workspace_size(32768, 10**6) == 0  # one tile: none
+    assert lib.ccl_label_csr_workspace_size(0, 0) == 0
+    need = lib.ccl_label_csr_workspace_size(n, m)
+    args = (n, m, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), None, ctypes.c_void_p(1 << 28))
     assert lib.ccl_label_csr(*args, None, 0, None) == INVALID
-    assert lib.ccl_label_csr(*args, ctypes.c_void_p(1 << 30), 8, None) == INVALID
-    assert lib.ccl_label_csr(*args, ctypes.c_void_p((1 << 30) + 4), 1 << 20, None) == INVALID
-    assert lib.ccl_label_csr(-3, None, None, None, None, None, 0, None) == INVALID
-    assert lib.ccl_label_csr(0, None, None, None, None, None, 0, None) == 0
+    assert lib.ccl_label_csr(*args, ctypes.c_void_p(1 << 33), need - 8, None) == INVALID
+    assert lib.ccl_label_csr(*args, ctypes.c_void_p((1 << 33) + 4), need, None) == INVALID
+    assert lib.ccl_label_csr(-3, 0, None, None, None, None, None, 0, None) == INVALID
+    assert lib.ccl_label_csr(5, -1, None, None, None, None, None, 0, None) == INVALID
+    assert lib.ccl_label_csr(0, 0, None, None, None, None, None, 0, None) == 0
 
 
 def test_plan_argument_errors(lib):

@@ -210,7 +210,7 @@ def test_repeat_runs_identical(ccl):
     want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
     rp, c, o = dev(g.row_ptr), dev(g.col), dev(g.occ)
     out = torch.empty(g.n_sites, dtype=torch.int32, device="cuda")
-    ws = torch.empty(ccl.csr_workspace_bytes(g.n_sites), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ccl.csr_workspace_bytes(g.n_sites, len(g.col)), dtype=torch.uint8, device="cuda")
     _say("csr repeat x50")
     for _ in range(50):
         ccl.label_csr(rp, c, o, out=out, workspace=ws)
