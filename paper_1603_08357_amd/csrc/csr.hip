@@ -61,18 +61,35 @@ __device__ __forceinline__ int32_t affine_row(int32_t e, int32_t d) {
   }
 }
 
-// Join bond (t, v) of the tile (t tile-relative, v global) or record it as
-// leaving: `pairs` is the tile's segment, `n_out` the LDS slot counter.
-__device__ __forceinline__ void tile_bond(int32_t* par, int32_t t, int32_t v, int64_t lo,
-                                          int32_t cnt, int2* pairs, uint32_t* n_out) {
+// Join bond (t, v) of the tile (t tile-relative, v global) in LDS, or, when v
+// lies outside the tile, count it and return true (the caller records it).
+__device__ __forceinline__ bool tile_bond(int32_t* par, int32_t t, int32_t v, int64_t lo,
+                                          int32_t cnt) {
   const int64_t vl = (int64_t)v - lo;
   if (vl >= 0 && vl < cnt) {
     lds_unite(par, t, (int32_t)vl);
-  } else {
-    const uint32_t slot =
-        __hip_atomic_fetch_add(n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    pairs[slot] = make_int2((int32_t)(lo + t), v);
+    return false;
   }
+  return true;
+}
+
+// Reserve `mine` consecutive slots of the tile's pair segment for this lane:
+// one LDS atomic per wavefront (inclusive scan of the lanes' counts with
+// cross-lane shuffles).  Returns the lane's first slot.
+__device__ __forceinline__ uint32_t reserve_slots(uint32_t mine, uint32_t* n_out) {
+  const int lane = threadIdx.x & 63;
+  uint32_t incl = mine;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t up = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += up;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane == 63 && total)
+    base = __hip_atomic_fetch_add(n_out, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  base = __shfl(base, 63, 64);
+  return base + incl - mine;
 }
 
 // One workgroup per tile.
@@ -158,6 +175,7 @@ __global__ void __launch_bounds__(kTileBlock)
         ra[k] = buf_i32(rp, 4u * t) - e_begin;
         rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
       }
+      uint32_t leave = 0;  // bit 4j+c: bond (j, c) leaves the tile
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int32_t e = cb + 4 * (j * kTileBlock + tid);
@@ -165,13 +183,32 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           if (((ov[j] >> (8 * c)) & 0xFFu) == 0) continue;
-          tile_bond(par, affine_row(e + c, deg), c4[c], lo, cnt, my_pairs, &n_out);
+          if (tile_bond(par, affine_row(e + c, deg), c4[c], lo, cnt)) leave |= 1u << (4 * j + c);
         }
+      }
+      uint32_t slot = reserve_slots(__popc(leave), &n_out);
+      while (leave) {
+        const int bit = __ffs(leave) - 1;
+        leave &= leave - 1;
+        const int j = bit >> 2, c = bit & 3;
+        const int32_t e = cb + 4 * (j * kTileBlock + tid) + c;
+        const int32_t v = c == 0 ? cv[j].x : c == 1 ? cv[j].y : c == 2 ? cv[j].z : cv[j].w;
+        my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e, deg)), v);
+      }
+      // the group of four bonds that straddles the end of the tile (one lane)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t e = cb + 4 * (j * kTileBlock + tid);
         if (j < deg && e < ce && e + 4 > ce) {
           for (int32_t x = e; x < ce; ++x) {
             const int64_t ge = (int64_t)e_begin + x;
             if (HAS_OCC && occ[ge] == 0) continue;
-            tile_bond(par, affine_row(x, deg), col[ge], lo, cnt, my_pairs, &n_out);
+            const int32_t v = col[ge];
+            if (tile_bond(par, affine_row(x, deg), v, lo, cnt)) {
+              const uint32_t sl =
+                  __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, deg)), v);
+            }
           }
         }
       }
@@ -195,17 +232,42 @@ __global__ void __launch_bounds__(kTileBlock)
         na[k] = buf_i32(rp, 4u * t) - e_begin;
         nb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
       }
+      uint32_t leave = 0;  // bit kDegFast*k+j: register bond (k, j) leaves the tile
 #pragma unroll
       for (int k = 0; k < kRowsPerThread; ++k) {
         const int t = base + k * kTileBlock + tid;
         if (t >= cnt) continue;
 #pragma unroll
         for (int j = 0; j < kDegFast; ++j)
-          if (ov[k][j] != 0) tile_bond(par, t, cv[k][j], lo, cnt, my_pairs, &n_out);
+          if (ov[k][j] != 0 && tile_bond(par, t, cv[k][j], lo, cnt)) leave |= 1u << (kDegFast * k + j);
+      }
+      uint32_t slot = reserve_slots(__popc(leave), &n_out);
+      while (leave) {
+        const int bit = __ffs(leave) - 1;
+        leave &= leave - 1;
+        const int k = bit / kDegFast, j = bit % kDegFast;
+        int32_t v = 0;
+#pragma unroll
+        for (int kk = 0; kk < kRowsPerThread; ++kk)
+#pragma unroll
+          for (int jj = 0; jj < kDegFast; ++jj)
+            if (kk == k && jj == j) v = cv[kk][jj];
+        my_pairs[slot++] = make_int2((int32_t)(lo + base + k * kTileBlock + tid), v);
+      }
+      // rows longer than kDegFast: the rest of their bonds one by one
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int t = base + k * kTileBlock + tid;
+        if (t >= cnt) continue;
         for (int32_t e = ra[k] + (fast ? kDegFast : 0); e < rb[k]; ++e) {
           const int64_t ge = (int64_t)e_begin + e;
           if (HAS_OCC && occ[ge] == 0) continue;
-          tile_bond(par, t, col[ge], lo, cnt, my_pairs, &n_out);
+          const int32_t v = col[ge];
+          if (tile_bond(par, t, v, lo, cnt)) {
+            const uint32_t sl =
+                __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            my_pairs[sl] = make_int2((int32_t)(lo + t), v);
+          }
         }
       }
 #pragma unroll
@@ -222,35 +284,65 @@ __global__ void __launch_bounds__(kTileBlock)
 
 // Cross kernel: one workgroup per tile (tiles renumbered so that each XCD
 // takes a contiguous range of them and its L2 holds the neighbouring tiles
-// those joins touch).  Lanes take four leaving bonds at a time, request the
-// first parent of all eight ends together, then chase and join.
+// those joins touch).  A lane carries kPairsInFlight leaving bonds through the
+// join in lockstep: the first parents of all their ends are requested
+// together, each chase round advances every unfinished chase by one link,
+// and the first atomicMin of every join is issued back to back.  Joins whose
+// atomicMin displaced a link finish with the sequential loop.  Interleaving
+// the joins of one lane is just one more schedule of Algorithm 1, which is
+// correct under any interleaving.
+constexpr int kPairsInFlight = 8;
+constexpr int kChaseRounds = 4;
+
 __global__ void __launch_bounds__(256)
     k_csr_cross(const int2* __restrict__ pairs, const int2* __restrict__ seg, int32_t* label) {
   const uint32_t tile = xcd_block_id();
   const int2 sc = seg[tile];
   const int2* p = pairs + sc.x;
   const int32_t count = sc.y;
-  for (int32_t i = 4 * threadIdx.x; i < count; i += 4 * 256) {
-    int32_t u[4], v[4], pu[4], pv[4];
+  constexpr int P = kPairsInFlight;
+  for (int32_t i0 = P * threadIdx.x; i0 < count; i0 += P * 256) {
+    int32_t a[P], b[P], pa[P], pb[P];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int2 e = i + k < count ? p[i + k] : make_int2(0, 0);
-      u[k] = e.x;
-      v[k] = e.y;
+    for (int k = 0; k < P; ++k) {
+      // clamped index: every load is issued unconditionally (no branch, no
+      // wait between them); pairs past the end become (0, 0), a no-op
+      const int2 e = p[min(i0 + k, count - 1)];
+      const bool in = i0 + k < count;
+      a[k] = in ? e.x : 0;
+      b[k] = in ? e.y : 0;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bool in = i + k < count;
-      pu[k] = in ? lab_ld(label + u[k]) : u[k];
-      pv[k] = in ? lab_ld(label + v[k]) : v[k];
+    for (int k = 0; k < P; ++k) {
+      pa[k] = lab_ld(label + a[k]);
+      pb[k] = lab_ld(label + b[k]);
+    }
+    // lockstep chase: after round r every chase of length <= r + 1 is done
+#pragma unroll
+    for (int r = 0; r < kChaseRounds; ++r) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        // branch-free: a finished chase re-reads its root (a cache hit)
+        a[k] = pa[k];
+        b[k] = pb[k];
+        pa[k] = lab_ld(label + a[k]);
+        pb[k] = lab_ld(label + b[k]);
+      }
+    }
+    int32_t hi[P], lo[P], old[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      // longer chases finish sequentially, with path halving
+      if (pa[k] != a[k]) a[k] = find_root_halving_from(label, a[k], pa[k]);
+      if (pb[k] != b[k]) b[k] = find_root_halving_from(label, b[k], pb[k]);
+      hi[k] = max(a[k], b[k]);
+      lo[k] = min(a[k], b[k]);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i + k >= count) continue;
-      const int32_t r1 = find_root_halving_from(label, u[k], pu[k]);
-      const int32_t r2 = find_root_halving_from(label, v[k], pv[k]);
-      if (r1 != r2) join_roots(label, r1, r2);
-    }
+    for (int k = 0; k < P; ++k) old[k] = hi[k] != lo[k] ? lab_min(label + hi[k], lo[k]) : lo[k];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (old[k] != lo[k] && old[k] != hi[k]) join_roots(label, old[k], lo[k]);
   }
 }
 

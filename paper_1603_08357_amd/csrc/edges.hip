@@ -81,40 +81,67 @@ __global__ void __launch_bounds__(kBlock)
 // non-root label behind -- so the chase itself stores nothing else.
 template <bool VEC>
 __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
+  constexpr int G = 4;  // 16-byte groups per lane per iteration
   const int64_t groups = (n + 3) >> 2;
   const int64_t per = (groups + gridDim.x - 1) / gridDim.x;
   const int64_t g0 = (int64_t)xcd_block_id() * per;
   const int64_t g1 = min(g0 + per, groups);
-  for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) {
-    const int64_t i0 = g << 2;
-    if (VEC && i0 + 3 < n) {
-      int4 v = reinterpret_cast<const int4*>(label)[g];
-      int32_t* c = reinterpret_cast<int32_t*>(&v);
-      // the four parents' labels, requested together (every label is a
-      // valid index, so the loads need no guard)
-      int32_t q[4];
+  const int64_t full = VEC ? (n >> 2) : 0;  // groups with all four sites in range
+  for (int64_t gb = g0; gb < g1; gb += G * kBlock) {
+    int4 v[G];
+    int32_t q[G][4];
+    // the lane's groups gb + j*kBlock + tid, then all sixteen parents' labels
 #pragma unroll
-      for (int j = 0; j < 4; ++j) q[j] = lab_ld(label + c[j]);
-      bool changed = false;
+    for (int j = 0; j < G; ++j) {
+      // clamped index keeps the loads unconditional; groups outside the
+      // vector range are replaced by the identity (nothing to do)
+      const int64_t g = gb + j * kBlock + threadIdx.x;
+      const int4 ld = reinterpret_cast<const int4*>(label)[full > 0 ? min(g, full - 1) : 0];
+      const bool in = g < g1 && g < full;
+      v[j] = in ? ld : make_int4((int32_t)(4 * g), (int32_t)(4 * g + 1), (int32_t)(4 * g + 2),
+                                 (int32_t)(4 * g + 3));
+    }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t p = c[j];
-        if (p == (int32_t)(i0 + j) || q[j] == p) continue;
-        const int32_t r = find_root(label, q[j]);
-        if (r != q[j]) lab_st(label + p, r);
-        c[j] = r;
-        changed = true;
+    for (int j = 0; j < G; ++j) {
+      const int32_t* c = reinterpret_cast<const int32_t*>(&v[j]);
+      const int64_t i0 = (gb + j * kBlock + threadIdx.x) << 2;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // unconditional load (index 0 when nothing is needed) keeps the
+        // sixteen loads free of branches, so they are all in flight at once
+        const bool need = c[t] != (int32_t)(i0 + t);
+        const int32_t got = lab_ld(label + (need ? c[t] : 0));
+        q[j][t] = need ? got : c[t];
       }
-      if (changed) reinterpret_cast<int4*>(label)[g] = v;
-    } else {
-      for (int64_t i = i0; i < min(i0 + 4, n); ++i) {
-        const int32_t p = lab_ld(label + i);
-        if (p == (int32_t)i) continue;
-        const int32_t q = lab_ld(label + p);
-        if (q == p) continue;
-        const int32_t r = find_root(label, q);
-        if (r != q) lab_st(label + p, r);
-        lab_st(label + i, r);
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int64_t g = gb + j * kBlock + threadIdx.x;
+      if (g >= g1) continue;
+      const int64_t i0 = g << 2;
+      if (g < full) {
+        int32_t* c = reinterpret_cast<int32_t*>(&v[j]);
+        bool changed = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int32_t p = c[t];
+          if (p == (int32_t)(i0 + t) || q[j][t] == p) continue;
+          const int32_t r = find_root(label, q[j][t]);
+          if (r != q[j][t]) lab_st(label + p, r);
+          c[t] = r;
+          changed = true;
+        }
+        if (changed) reinterpret_cast<int4*>(label)[g] = v[j];
+      } else {
+        for (int64_t i = i0; i < min(i0 + 4, n); ++i) {
+          const int32_t p = lab_ld(label + i);
+          if (p == (int32_t)i) continue;
+          const int32_t qq = lab_ld(label + p);
+          if (qq == p) continue;
+          const int32_t r = find_root(label, qq);
+          if (r != qq) lab_st(label + p, r);
+          lab_st(label + i, r);
+        }
       }
     }
   }
