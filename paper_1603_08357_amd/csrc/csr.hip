@@ -187,13 +187,16 @@ __global__ void __launch_bounds__(kTileBlock)
         }
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
-      while (leave) {
-        const int bit = __ffs(leave) - 1;
-        leave &= leave - 1;
-        const int j = bit >> 2, c = bit & 3;
-        const int32_t e = cb + 4 * (j * kTileBlock + tid) + c;
-        const int32_t v = c == 0 ? cv[j].x : c == 1 ? cv[j].y : c == 2 ? cv[j].z : cv[j].w;
-        my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e, deg)), v);
+      if (leave) {  // static indices only: the register arrays must not spill
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int32_t e = cb + 4 * (j * kTileBlock + tid);
+          const int32_t c4[4] = {cv[j].x, cv[j].y, cv[j].z, cv[j].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if ((leave >> (4 * j + c)) & 1u)
+              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + c, deg)), c4[c]);
+        }
       }
       // the group of four bonds that straddles the end of the tile (one lane)
 #pragma unroll
@@ -242,17 +245,13 @@ __global__ void __launch_bounds__(kTileBlock)
           if (ov[k][j] != 0 && tile_bond(par, t, cv[k][j], lo, cnt)) leave |= 1u << (kDegFast * k + j);
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
-      while (leave) {
-        const int bit = __ffs(leave) - 1;
-        leave &= leave - 1;
-        const int k = bit / kDegFast, j = bit % kDegFast;
-        int32_t v = 0;
+      if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
-        for (int kk = 0; kk < kRowsPerThread; ++kk)
+        for (int k = 0; k < kRowsPerThread; ++k)
 #pragma unroll
-          for (int jj = 0; jj < kDegFast; ++jj)
-            if (kk == k && jj == j) v = cv[kk][jj];
-        my_pairs[slot++] = make_int2((int32_t)(lo + base + k * kTileBlock + tid), v);
+          for (int j = 0; j < kDegFast; ++j)
+            if ((leave >> (kDegFast * k + j)) & 1u)
+              my_pairs[slot++] = make_int2((int32_t)(lo + base + k * kTileBlock + tid), cv[k][j]);
       }
       // rows longer than kDegFast: the rest of their bonds one by one
 #pragma unroll

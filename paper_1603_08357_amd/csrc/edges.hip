@@ -174,8 +174,11 @@ ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const in
   ccl_status st = launch_init(n, label, s, d);
   if (st != CCL_OK) return st;
   if (m > 0) {
+    // four bonds per lane only when that still fills the grid twice over: a
+    // small graph needs every lane it can get to hide the chase latency
+    const int64_t lanes = (int64_t)d.cu_count * 8 * kBlock;
     const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0 &&
-                     (reinterpret_cast<uintptr_t>(occ) & 3) == 0;
+                     (reinterpret_cast<uintptr_t>(occ) & 3) == 0 && m >= 8 * lanes;
     const unsigned g = grid_for(vec ? (m + 3) / 4 : m, kBlock, 8, d);
     if (vec && occ)
       CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, true>), g, kBlock, 0, s, src, dst, occ, m, label);

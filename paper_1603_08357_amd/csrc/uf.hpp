@@ -148,4 +148,63 @@ __device__ __forceinline__ void lds_unite(int32_t* par, int32_t a, int32_t b) {
   }
 }
 
+// ---------------------------------------------------------------- LDS, 16-bit
+
+// A tile of up to 65536 sites keeps its parent array as 16-bit tile-relative
+// ids (128 KB of LDS).  Loads and path-halving stores are 16-bit LDS accesses;
+// LDS has no 16-bit atomic min, so the min is a compare-and-swap loop on the
+// 32-bit word holding the entry (the neighbouring entry's concurrent 16-bit
+// stores just make the swap retry).
+
+__device__ __forceinline__ int32_t lds16_ld(const uint16_t* p) {
+  return (int32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds16_st(uint16_t* p, int32_t v) {
+  __hip_atomic_store(p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// atomicMin of entry x with v; returns the previous value of the entry
+__device__ __forceinline__ int32_t lds16_min(uint16_t* par, int32_t x, int32_t v) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(par) + (x >> 1);
+  const uint32_t sh = (uint32_t)(x & 1) * 16u;
+  uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (;;) {
+    const uint32_t old = (cur >> sh) & 0xFFFFu;
+    if ((int32_t)old <= v) return (int32_t)old;
+    const uint32_t next = (cur & ~(0xFFFFu << sh)) | ((uint32_t)v << sh);
+    uint32_t seen = cur;
+    if (__hip_atomic_compare_exchange_strong(w, &seen, next, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return (int32_t)old;
+    cur = seen;
+  }
+}
+
+__device__ __forceinline__ int32_t lds16_find(uint16_t* par, int32_t x) {
+  int32_t p = lds16_ld(par + x);
+  while (p != x) {
+    const int32_t g = lds16_ld(par + p);
+    if (g == p) return p;
+    lds16_st(par + x, g);
+    x = g;
+    p = lds16_ld(par + x);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void lds16_unite(uint16_t* par, int32_t a, int32_t b) {
+  int32_t r1 = lds16_find(par, a);
+  int32_t r2 = lds16_find(par, b);
+  while (r1 != r2) {
+    if (r1 < r2) {
+      const int32_t t = r1;
+      r1 = r2;
+      r2 = t;
+    }
+    const int32_t old = lds16_min(par, r1, r2);
+    if (old == r2 || old == r1) break;
+    r1 = old;
+  }
+}
+
 }  // namespace ccl
