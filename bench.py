@@ -115,7 +115,8 @@ def ingest_counters(fetch_csv: str, write_csv: str, workload: str) -> dict:
             for row in csv.DictReader(f):
                 if row.get("Counter_Name", counter) != counter:
                     continue
-                name = row["Kernel_Name"].split("(")[0].split("<")[0].replace("ccl::", "")
+                name = row["Kernel_Name"].split("(")[0].split("<")[0]
+                name = name.replace("void ", "").replace("ccl::", "").strip()
                 vals[name].append(float(row["Counter_Value"]) * 1024.0)
         return {k: sum(v) / len(v) for k, v in vals.items()}
 

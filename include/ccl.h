@@ -69,9 +69,9 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
                      const uint8_t* occupied, int32_t* labels_out, void* stream);
 
 /*
- * Workspace bytes ccl_label_csr needs: zero for n_sites <= 32768 (one tile),
+ * Workspace bytes ccl_label_csr needs: zero for n_sites <= 65536 (one tile),
  * else one 8-byte slot per bond (the bonds leaving their tile are collected
- * there) plus 8 bytes per 32768-site tile, rounded up to 256 bytes.
+ * there) plus 8 bytes per 65536-site tile, rounded up to 256 bytes.
  */
 size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds);
 
@@ -91,7 +91,7 @@ size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds);
  *              n_bonds) bytes, 8-byte aligned, contents need not be
  *              initialised and are garbage afterwards; may be NULL when that
  *              size is zero
- * Kernels: sites are cut into tiles of 32768 consecutive ids; one workgroup
+ * Kernels: sites are cut into tiles of 65536 consecutive ids; one workgroup
  * per tile initialises its labels (step i) and joins the tile-internal bonds
  * in LDS (step iii on the tile), recording the bonds that leave the tile in
  * the workspace; then those bonds are joined in global memory (step iii,

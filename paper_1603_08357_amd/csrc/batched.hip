@@ -41,6 +41,7 @@
 namespace ccl {
 
 enum : uint32_t { kItemSmall = 0, kItemInit = 1, kItemMerge = 2, kItemFlatten = 3 };
+constexpr int kLockstep = 4;  // bonds a lane carries through one lockstep join
 enum : int32_t { kScheduleDefault = 0, kScheduleFused = 1, kSchedulePhased = 2 };
 
 __host__ __device__ inline uint64_t pack_item(uint32_t inst, uint32_t kind, uint32_t chunk) {
@@ -89,33 +90,11 @@ __device__ __forceinline__ int32_t find_root_checked(const int32_t* lab, int32_t
   return x;
 }
 
-// The merge step's chase: path halving (see find_root_halving), with the
-// same refusal of labels that point upward or below zero.
-__device__ __forceinline__ int32_t find_root_halving_checked(int32_t* lab, int32_t x, bool& bad) {
-  int32_t p = lab_ld(lab + x);
-  while (p != x) {
-    if (p > x || p < 0) {
-      bad = true;
-      return x;
-    }
-    const int32_t g = lab_ld(lab + p);
-    if (g == p) return p;
-    if (g > p || g < 0) {
-      bad = true;
-      return x;
-    }
-    lab_st(lab + x, g);
-    x = g;
-    p = lab_ld(lab + x);
-  }
-  return x;
-}
-
 // Algorithm 1 with the same refusal: a returned old value above r1 or below
 // zero cannot come from a valid forest.
 __device__ __forceinline__ void unite_checked(int32_t* lab, int32_t a, int32_t b, bool& bad) {
-  int32_t r1 = find_root_halving_checked(lab, a, bad);
-  int32_t r2 = find_root_halving_checked(lab, b, bad);
+  int32_t r1 = find_root_halving_checked(lab, a, lab_ld(lab + a), bad);
+  int32_t r2 = find_root_halving_checked(lab, b, lab_ld(lab + b), bad);
   while (!bad && r1 != r2) {
     if (r1 < r2) {
       int32_t t = r1;
@@ -214,10 +193,24 @@ __global__ void k_batched(BatchArgs a) {
       const bool go =
           !a.fused || wait_count(a, a.init_done + k, n_chunks(n, a.sites_per_chunk), &ok_slot);
       if (go) {
+        // kLockstep bonds per lane at a time (bond lo + (s*kLockstep + k) *
+        // blockDim + tid: each load instruction coalesced), joined in lockstep
         const int64_t lo = (int64_t)c * a.bonds_per_chunk;
         const int64_t hi = min(lo + a.bonds_per_chunk, m);
-        for (int64_t b = lo + threadIdx.x; b < hi && !bad; b += blockDim.x)
-          if (occ == nullptr || occ[b] != 0) unite_checked(lab, src[b], dst[b], bad);
+        const int64_t step = (int64_t)kLockstep * blockDim.x;
+        for (int64_t b0 = lo; b0 < hi && !bad; b0 += step) {
+          int32_t u[kLockstep], v[kLockstep];
+#pragma unroll
+          for (int k = 0; k < kLockstep; ++k) {
+            const int64_t b = b0 + (int64_t)k * blockDim.x + threadIdx.x;
+            const int64_t bc = b < hi ? b : lo;  // clamped: loads stay unconditional
+            const bool on = b < hi && (occ == nullptr || occ[bc] != 0);
+            const int32_t x = src[bc], y = dst[bc];
+            u[k] = on ? x : 0;  // (0, 0) is a no-op
+            v[k] = on ? y : 0;
+          }
+          unite_lockstep<kLockstep, 2, true>(lab, u, v, bad);
+        }
       }
       if (a.fused) signal_done(a.merge_done + k);
     } else {

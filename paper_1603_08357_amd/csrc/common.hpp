@@ -104,7 +104,7 @@ ccl_status launch_validate_csr(int64_t n, const int32_t* row_ptr, const int32_t*
 ccl_status launch_probe_copy(const void* in, void* out, size_t bytes, hipStream_t s,
                              const DeviceInfo& d);
 
-// Sites per tile of the CSR path (one workgroup, one LDS slot per site).
-constexpr int kCsrTile = 32768;
+// Sites per tile of the CSR path (one workgroup, a 16-bit LDS slot per site).
+constexpr int kCsrTile = 65536;
 
 }  // namespace ccl

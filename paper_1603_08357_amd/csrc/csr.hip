@@ -1,9 +1,10 @@
 // CSR labeling with tile-local joins in LDS.
 //
-// Sites are cut into tiles of kCsrTile consecutive ids; a tile owns its sites
+// Sites are cut into tiles of kCsrTile (65536) consecutive ids; a tile owns its sites
 // and the bonds stored in its rows.  Three kernels:
 //   1. tile kernel, one workgroup per tile: step (i) for the tile in LDS
-//      (par[t] = t), step (iii) -- Algorithm 1 on LDS with ds_min -- for every
+//      (par[t] = t, 16-bit tile-relative entries: 128 KB), step (iii) --
+//      Algorithm 1 on LDS, its atomicMin a 32-bit compare-and-swap -- for every
 //      occupied bond whose two ends lie in the tile, a root chase in LDS, and
 //      one coalesced store of the tile's labels (each site's tile-local root,
 //      the tile's minimum member of its local cluster).  Occupied bonds that
@@ -22,7 +23,7 @@
 namespace ccl {
 
 constexpr int kTileBlock = 1024;
-constexpr int kTileShift = 15;
+constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
@@ -63,11 +64,11 @@ __device__ __forceinline__ int32_t affine_row(int32_t e, int32_t d) {
 
 // Join bond (t, v) of the tile (t tile-relative, v global) in LDS, or, when v
 // lies outside the tile, count it and return true (the caller records it).
-__device__ __forceinline__ bool tile_bond(int32_t* par, int32_t t, int32_t v, int64_t lo,
+__device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, int64_t lo,
                                           int32_t cnt) {
   const int64_t vl = (int64_t)v - lo;
   if (vl >= 0 && vl < cnt) {
-    lds_unite(par, t, (int32_t)vl);
+    lds16_unite(par, t, (int32_t)vl);
     return false;
   }
   return true;
@@ -92,24 +93,26 @@ __device__ __forceinline__ uint32_t reserve_slots(uint32_t mine, uint32_t* n_out
   return base + incl - mine;
 }
 
-// One workgroup per tile.
-// Affine path (the tile's row_ptr is e_begin + d*r with 1 <= d <= 4, checked
-// row by row from the same loads): each iteration takes kChunkRows rows and
-// their d*kChunkRows bonds; lane tid loads bonds 4q..4q+3 (q = j*kTileBlock +
-// tid, j < d) with one 16-byte col load and one 4-byte occ load, so every
-// load instruction is a fully coalesced vector load.
-// Row path (any other CSR): kRowsPerThread rows per lane, the first kDegFast
-// bonds of each row in one batch of buffer loads, longer rows in a loop.
-// Either way the next iteration's row_ptr loads are issued before this one's
-// joins.  Buffer resources are based at the tile's first row and first bond,
-// so offsets stay small whatever the graph size; a tile with 2^30 or more
-// bonds uses plain loads.
+// One workgroup per tile, in two phases.
+// A. Is the tile affine (row_ptr[lo + t] = e_begin + d*t, 1 <= d <= 4)?  Every
+//    lane checks a strided share of the tile's row_ptr; one vote.
+// B. Affine tiles stream their d*cnt bonds in groups of four: lane tid takes
+//    groups (2k+u)*kTileBlock + tid (u = 0, 1) at iteration k with one 16-byte
+//    col load and one 4-byte occ load per group, both fully coalesced, and
+//    requests iteration k+1's groups before joining iteration k's, so no
+//    barrier or wait on another wavefront is ever on the way.  Other CSR
+//    graphs take the row path: kRowsPerThread rows per lane, the first
+//    kDegFast bonds of each row in one batch of buffer loads (longer rows in a
+//    loop), the next rows' row_ptr requested ahead.
+// Buffer resources are based at the tile's first row and first bond, so
+// offsets stay small whatever the graph size; a tile with 2^30 or more bonds
+// uses plain loads.
 template <bool HAS_OCC>
 __global__ void __launch_bounds__(kTileBlock)
     k_csr_tile(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
                int2* __restrict__ pairs, int2* __restrict__ seg) {
-  __shared__ int32_t par[kCsrTile];
+  __shared__ uint16_t par[kCsrTile];  // tile-relative parents, 16 bits each
   __shared__ uint32_t n_out;
   const int64_t lo = (int64_t)blockIdx.x << kTileShift;
   const int32_t cnt = (int32_t)min((int64_t)kCsrTile, n - lo);
@@ -129,93 +132,96 @@ __global__ void __launch_bounds__(kTileBlock)
   const __amdgpu_buffer_rsrc_t ro =
       make_rsrc(HAS_OCC ? occ + e_begin : nullptr, fast && HAS_OCC ? (uint32_t)e_count : 0u);
 
-  for (int t = tid; t < kCsrTile; t += kTileBlock) par[t] = t;
+  for (int w = tid; w < kCsrTile / 2; w += kTileBlock)  // par[t] = t, two entries per word
+    reinterpret_cast<uint32_t*>(par)[w] = (uint32_t)(2 * w) | ((uint32_t)(2 * w + 1) << 16);
   if (tid == 0) n_out = 0;
 
-  // row_ptr of this lane's rows in the first chunk (relative to e_begin);
-  // rows past the tile read 0 or the end value and so hold no bonds
-  int32_t ra[kRowsPerThread], rb[kRowsPerThread];
+  // ---- A: affine check (rows 0..cnt of row_ptr; out-of-range reads are 0)
+  bool ok = affine_try;
+  if (affine_try) {
+    constexpr int kBatch = 16;
+    for (int t0 = 0; t0 <= cnt; t0 += kBatch * kTileBlock) {
+      int32_t v[kBatch];
 #pragma unroll
-  for (int k = 0; k < kRowsPerThread; ++k) {
-    const uint32_t t = (uint32_t)(k * kTileBlock + tid);
-    ra[k] = buf_i32(rp, 4u * t) - e_begin;
-    rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
-  }
-  __syncthreads();
-
-  bool affine = affine_try;
-  for (int base = 0; base < cnt; base += kChunkRows) {
-    // is this chunk affine?  (every lane checks its rows; one vote)
-    bool ok = true;
+      for (int k = 0; k < kBatch; ++k) v[k] = buf_i32(rp, 4u * (uint32_t)(t0 + k * kTileBlock + tid));
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      const int32_t t = base + k * kTileBlock + tid;
-      if (t < cnt) ok = ok && ra[k] == deg * t && rb[k] == deg * (t + 1);
+      for (int k = 0; k < kBatch; ++k) {
+        const int32_t t = t0 + k * kTileBlock + tid;
+        if (t <= cnt) ok = ok && v[k] - e_begin == deg * t;
+      }
     }
-    affine = __syncthreads_and(affine && ok) != 0;
+  }
+  const bool affine = __syncthreads_and(ok) != 0;  // also publishes the LDS init
 
-    if (affine) {
-      const int32_t cb = deg * base;                                     // chunk's first bond
-      const int32_t ce = deg * (int32_t)min(base + kChunkRows, (int)cnt);  // one past its last
-      int4 cv[4];
-      uint32_t ov[4];
+  if (affine) {
+    // ---- B, affine: bond groups of four
+    const int32_t nb = deg * cnt;
+    const int32_t full = nb >> 2;  // groups entirely inside the tile
+    const int32_t iters = (((nb + 3) >> 2) + 2 * kTileBlock - 1) / (2 * kTileBlock);
+    int4 c[2], cn[2];
+    uint32_t o[2], on[2];
+    auto load = [&](int32_t k, int u, int4& cv, uint32_t& ov) {
+      const int32_t q = (2 * k + u) * kTileBlock + tid;
+      const uint32_t off = q < full ? 4u * (uint32_t)q : kOffNone;
+      cv = buf_i32x4(rc, off * 4u);
+      ov = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
+    };
+    load(0, 0, c[0], o[0]);
+    load(0, 1, c[1], o[1]);
+    for (int32_t k = 0; k < iters; ++k) {
+      load(k + 1, 0, cn[0], on[0]);
+      load(k + 1, 1, cn[1], on[1]);
+      uint32_t leave = 0;  // bit 4u+j: bond j of group u leaves the tile
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        // whole groups of four bonds only: the (at most one) group that
-        // straddles the end of the tile is read below with plain loads
-        const int32_t e = cb + 4 * (j * kTileBlock + tid);
-        const uint32_t off = (j < deg && e + 4 <= ce) ? (uint32_t)e : kOffNone;
-        cv[j] = buf_i32x4(rc, off * 4u);
-        ov[j] = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
-      }
-      // next chunk's row_ptr for its check
+      for (int u = 0; u < 2; ++u) {
+        const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
+        const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        const uint32_t t = (uint32_t)(base + kChunkRows + k * kTileBlock + tid);
-        ra[k] = buf_i32(rp, 4u * t) - e_begin;
-        rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
-      }
-      uint32_t leave = 0;  // bit 4j+c: bond (j, c) leaves the tile
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t e = cb + 4 * (j * kTileBlock + tid);
-        const int32_t c4[4] = {cv[j].x, cv[j].y, cv[j].z, cv[j].w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (((ov[j] >> (8 * c)) & 0xFFu) == 0) continue;
-          if (tile_bond(par, affine_row(e + c, deg), c4[c], lo, cnt)) leave |= 1u << (4 * j + c);
-        }
+        for (int j = 0; j < 4; ++j)
+          if (((o[u] >> (8 * j)) & 0xFFu) != 0 && tile_bond(par, affine_row(e + j, deg), c4[j], lo, cnt))
+            leave |= 1u << (4 * u + j);
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int32_t e = cb + 4 * (j * kTileBlock + tid);
-          const int32_t c4[4] = {cv[j].x, cv[j].y, cv[j].z, cv[j].w};
+        for (int u = 0; u < 2; ++u) {
+          const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
+          const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            if ((leave >> (4 * j + c)) & 1u)
-              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + c, deg)), c4[c]);
+          for (int j = 0; j < 4; ++j)
+            if ((leave >> (4 * u + j)) & 1u)
+              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + j, deg)), c4[j]);
         }
       }
-      // the group of four bonds that straddles the end of the tile (one lane)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int32_t e = cb + 4 * (j * kTileBlock + tid);
-        if (j < deg && e < ce && e + 4 > ce) {
-          for (int32_t x = e; x < ce; ++x) {
-            const int64_t ge = (int64_t)e_begin + x;
-            if (HAS_OCC && occ[ge] == 0) continue;
-            const int32_t v = col[ge];
-            if (tile_bond(par, affine_row(x, deg), v, lo, cnt)) {
-              const uint32_t sl =
-                  __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-              my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, deg)), v);
-            }
-          }
+      for (int u = 0; u < 2; ++u) {
+        c[u] = cn[u];
+        o[u] = on[u];
+      }
+    }
+    // the last group, when it straddles the end of the tile
+    if (tid == 0 && full * 4 < nb) {
+      for (int32_t x = 4 * full; x < nb; ++x) {
+        const int64_t ge = (int64_t)e_begin + x;
+        if (HAS_OCC && occ[ge] == 0) continue;
+        const int32_t v = col[ge];
+        if (tile_bond(par, affine_row(x, deg), v, lo, cnt)) {
+          const uint32_t sl =
+              __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, deg)), v);
         }
       }
-    } else {
+    }
+  } else {
+    // ---- B, rows
+    int32_t ra[kRowsPerThread], rb[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const uint32_t t = (uint32_t)(k * kTileBlock + tid);
+      ra[k] = buf_i32(rp, 4u * t) - e_begin;
+      rb[k] = buf_i32(rp, 4u * (t + 1)) - e_begin;
+    }
+    for (int base = 0; base < cnt; base += kChunkRows) {
       int32_t cv[kRowsPerThread][kDegFast];
       uint32_t ov[kRowsPerThread][kDegFast];
 #pragma unroll
@@ -277,7 +283,7 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   __syncthreads();
-  for (int t = tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds_find(par, t));
+  for (int t = tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds16_find(par, t));
   if (tid == 0 && seg != nullptr) seg[blockIdx.x] = make_int2(e_begin - e0, (int32_t)n_out);
 }
 
@@ -345,6 +351,47 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Step (iv) for the CSR path: one workgroup per window of kFlatWin sites,
+// staged in LDS with 16-byte loads.  After the tile and cross kernels a
+// site's label is its tile-local root, usually inside the same window, so
+// the parent's label is an LDS read; only parents whose cluster was joined
+// across tiles need a chase in global memory, and its result is cached in
+// the window (every thread sharing that parent then finds the root in LDS).
+// Every value written is the site's final root; the window goes back with
+// 16-byte stores.  Windows are renumbered so each XCD takes a contiguous run.
+constexpr int kFlatWin = 32768;
+constexpr int kFlatBlock = 1024;
+
+__global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, int64_t n) {
+  __shared__ int32_t w[kFlatWin];
+  const int64_t w0 = (int64_t)xcd_block_id() * kFlatWin;
+  const int32_t cnt = (int32_t)min((int64_t)kFlatWin, n - w0);
+  const int tid = threadIdx.x;
+  const int32_t cnt4 = cnt >> 2;
+  const int4* src4 = reinterpret_cast<const int4*>(label + w0);
+  for (int32_t t = tid; t < cnt4; t += kFlatBlock) reinterpret_cast<int4*>(w)[t] = src4[t];
+  for (int32_t t = 4 * cnt4 + tid; t < cnt; t += kFlatBlock) w[t] = label[w0 + t];
+  __syncthreads();
+  for (int32_t t = tid; t < cnt; t += kFlatBlock) {
+    const int32_t p = lds_ld(w + t);
+    if (p == (int32_t)(w0 + t)) continue;  // a root
+    const int64_t pl = (int64_t)p - w0;
+    const bool inside = pl >= 0 && pl < cnt;
+    const int32_t q = inside ? lds_ld(w + pl) : lab_ld(label + p);
+    if (q == p) continue;  // the parent is a root: already final
+    const int32_t r = find_root(label, q);
+    if (inside)
+      lds_st(w + pl, r);  // the parent's final root, for the threads sharing it
+    else if (r != q)
+      lab_st(label + p, r);
+    lds_st(w + t, r);
+  }
+  __syncthreads();
+  int4* dst4 = reinterpret_cast<int4*>(label + w0);
+  for (int32_t t = tid; t < cnt4; t += kFlatBlock) dst4[t] = reinterpret_cast<const int4*>(w)[t];
+  for (int32_t t = 4 * cnt4 + tid; t < cnt; t += kFlatBlock) label[w0 + t] = w[t];
+}
+
 size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds) {
   if (n_sites <= kCsrTile) return 0;
   const int64_t n_tiles = (n_sites + kCsrTile - 1) / kCsrTile;
@@ -372,7 +419,10 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
                col, occ, label, pairs, seg);
   if (n_tiles == 1) return CCL_OK;
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, 256, 0, s, pairs, seg, label);
-  return launch_flatten(n, label, s, d);
+  if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
+  const unsigned n_win = (unsigned)((n + kFlatWin - 1) / kFlatWin);
+  CCL_LAUNCH("ccl_flatten", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);
+  return CCL_OK;
 }
 
 // ---------------------------------------------------------------- checks

@@ -107,6 +107,110 @@ __device__ __forceinline__ void unite(int32_t* label, int32_t a, int32_t b) {
   if (r1 != r2) join_roots(label, r1, r2);
 }
 
+// Checked variants (used where a publication error must not turn into a
+// hang): a label that points upward or below zero, or an atomicMin returning
+// such a value, cannot occur in a valid forest; it sets `bad` and stops.
+__device__ __forceinline__ int32_t find_root_halving_checked(int32_t* label, int32_t x, int32_t p,
+                                                             bool& bad) {
+  while (p != x) {
+    if (p > x || p < 0) {
+      bad = true;
+      return x;
+    }
+    const int32_t g = lab_ld(label + p);
+    if (g == p) return p;
+    if (g > p || g < 0) {
+      bad = true;
+      return x;
+    }
+    lab_st(label + x, g);
+    x = g;
+    p = lab_ld(label + x);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void join_roots_checked(int32_t* label, int32_t r1, int32_t r2, bool& bad) {
+  while (!bad && r1 != r2) {
+    if (r1 < r2) {
+      const int32_t t = r1;
+      r1 = r2;
+      r2 = t;
+    }
+    const int32_t old = lab_min(label + r1, r2);
+    if (old == r2 || old == r1) break;
+    if (old > r1 || old < 0) {
+      bad = true;
+      break;
+    }
+    r1 = old;
+  }
+}
+
+// Step (iii) for P bonds at once, in lockstep: the first parents of all 2P
+// ends are requested together, each of `rounds` chase rounds advances every
+// chase by one link (a finished chase re-reads its root, a cache hit, so the
+// rounds stay free of branches and their loads stay in flight together),
+// longer chases finish with path halving, and the first atomicMin of every
+// join is issued back to back; a join whose atomicMin displaced a link ends
+// with the sequential loop.  This is only another interleaving of Algorithm
+// 1, which is correct under any interleaving.  A bond with a[k] == b[k] is a
+// no-op (callers map unoccupied or padding bonds to (x, x) with x a valid
+// site).  CHECKED: labels that point upward or below zero (impossible in a
+// valid forest) set `bad` and stop that chase instead of following it.
+template <int P, int ROUNDS, bool CHECKED>
+__device__ __forceinline__ void unite_lockstep(int32_t* label, int32_t (&a)[P], int32_t (&b)[P],
+                                               bool& bad) {
+  int32_t pa[P], pb[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    pa[k] = lab_ld(label + a[k]);
+    pb[k] = lab_ld(label + b[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (CHECKED) {
+        if (pa[k] > a[k] || pa[k] < 0) { bad = true; pa[k] = a[k]; }
+        if (pb[k] > b[k] || pb[k] < 0) { bad = true; pb[k] = b[k]; }
+      }
+      a[k] = pa[k];
+      b[k] = pb[k];
+      pa[k] = lab_ld(label + a[k]);
+      pb[k] = lab_ld(label + b[k]);
+    }
+  }
+  int32_t hi[P], lo[P], old[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    if (CHECKED) {
+      if (pa[k] > a[k] || pa[k] < 0) { bad = true; pa[k] = a[k]; }
+      if (pb[k] > b[k] || pb[k] < 0) { bad = true; pb[k] = b[k]; }
+    }
+    if (CHECKED) {
+      if (pa[k] != a[k]) a[k] = find_root_halving_checked(label, a[k], pa[k], bad);
+      if (pb[k] != b[k]) b[k] = find_root_halving_checked(label, b[k], pb[k], bad);
+    } else {
+      if (pa[k] != a[k]) a[k] = find_root_halving_from(label, a[k], pa[k]);
+      if (pb[k] != b[k]) b[k] = find_root_halving_from(label, b[k], pb[k]);
+    }
+    hi[k] = max(a[k], b[k]);
+    lo[k] = min(a[k], b[k]);
+  }
+  if (CHECKED && bad) return;
+#pragma unroll
+  for (int k = 0; k < P; ++k) old[k] = hi[k] != lo[k] ? lab_min(label + hi[k], lo[k]) : lo[k];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    if (old[k] == lo[k] || old[k] == hi[k]) continue;
+    if (CHECKED)
+      join_roots_checked(label, old[k], lo[k], bad);
+    else
+      join_roots(label, old[k], lo[k]);
+  }
+}
+
 // ---------------------------------------------------------------- LDS
 
 __device__ __forceinline__ int32_t lds_ld(const int32_t* p) {

@@ -74,9 +74,10 @@ def test_host_side_argument_errors(lib):
                          ctypes.c_void_p(4096 + 8), None) == INVALID
     # CSR: > one tile needs a workspace of the right size and alignment
     n, m = 100_000, 300_000
-    n_tiles = (n + 32767) // 32768
+    n_tiles = (n + 65535) // 65536
     assert lib.ccl_label_csr_workspace_size(n, m) == (n_tiles * 8 + 255) // 256 * 256 + 8 * m
-    assert lib.ccl_label_csr_workspace_size(32768, 10**6) == 0  # one tile: none
+    assert lib.ccl_label_csr_workspace_size(65536, 10**6) == 0  # one tile: none
+    assert lib.ccl_label_csr_workspace_size(65537, 0) > 0
     assert lib.ccl_label_csr_workspace_size(0, 0) == 0
     need = lib.ccl_label_csr_workspace_size(n, m)
     args = (n, m, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), None, ctypes.c_void_p(1 << 28))

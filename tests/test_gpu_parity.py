@@ -108,9 +108,10 @@ def test_config1_honeycomb_l256(ccl):
     check_invariants(got, g.n_sites, g.src, g.dst, g.occ)
 
 
-@pytest.mark.parametrize("L,p", [(181, 0.3473), (300, 0.1736), (300, 0.5209), (512, 0.3473)])
+@pytest.mark.parametrize("L,p", [(181, 0.3473), (257, 0.3473), (300, 0.1736), (300, 0.5209),
+                                 (512, 0.3473), (700, 0.3473)])
 def test_triangle_csr_multi_tile(ccl, L, p):
-    """Several 32768-site tiles and a ragged last tile."""
+    """One tile (L=181), several 65536-site tiles and ragged last tiles."""
     g = gen.triangle_csr_realization(L, p, L)
     got = gpu_csr(ccl, g.row_ptr, g.col, g.occ)
     np.testing.assert_array_equal(got, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ))
