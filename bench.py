@@ -47,7 +47,7 @@ def alg_bytes_csr(kernel: str, n: int, m: int) -> float:
         return 4.0 * (n + 1) + 5.0 * m + 4.0 * n
     if kernel == "ccl_csr_cross":  # nothing the method itself must move
         return 0.0
-    if kernel == "ccl_flatten":  # labels read and written
+    if kernel in ("ccl_flatten", "ccl_flatten_window"):  # labels read and written
         return 8.0 * n
     return 0.0
 
@@ -97,7 +97,8 @@ def load_traffic(kernel: str, workload: str):
 
 COPY_PROBE_BYTES = 1 << 30  # the copy probe reads and writes this much
 KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
-                "k_flatten": "ccl_flatten", "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
+                "k_flatten": "ccl_flatten", "k_flatten_window": "ccl_flatten_window",
+                "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
 
 
 def ingest_counters(fetch_csv: str, write_csv: str, workload: str) -> dict:
@@ -161,6 +162,50 @@ def time_steps(fn, steps: int, warmup: int, stream):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def step_distribution(fn, steps: int, stream, before=None):
+    """Per-step HIP-event durations (ms): median, p99 and min.  `before`, if
+    given, runs ahead of each step outside the events (a cache flush)."""
+    import torch
+    times = []
+    for _ in range(steps):
+        if before is not None:
+            before()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    t = np.sort(np.asarray(times))
+    return {"median": round(float(np.median(t)), 5), "p99": round(float(np.quantile(t, 0.99)), 5),
+            "min": round(float(t[0]), 5), "steps": steps}
+
+
+def make_flush(nbytes=1 << 30):
+    """A 1 GiB device write that evicts the labels from L2 and the MALL."""
+    import torch
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    return lambda: buf.fill_(1)
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
 def traced_kernels(fn, steps: int):
     """Mean duration (ms) and launch count per kernel over `steps` steps."""
     import torch
@@ -206,10 +251,11 @@ def bench_csr(L, p, seed, steps, warmup):
     fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream)
     ms, wall = time_steps(fn, steps, warmup, stream)
     kern = traced_kernels(fn, steps)
-    return g, out, dict(n=n, m=m, ms=ms, wall=wall, kernels=kern)
+    dist = step_distribution(fn, steps, stream)
+    return g, out, dict(n=n, m=m, ms=ms, wall=wall, kernels=kern, step_ms=dist)
 
 
-def bench_edges(g, steps, warmup):
+def bench_edges(g, steps, warmup, cold=False):
     import torch
     import paper_1603_08357_amd as ccl
     src = torch.from_numpy(g.src).cuda()
@@ -220,7 +266,12 @@ def bench_edges(g, steps, warmup):
     fn = lambda: ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
     ms, wall = time_steps(fn, steps, warmup, stream)
     kern = traced_kernels(fn, steps)
-    return out, dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern)
+    res = dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern)
+    if cold:  # warm: back to back; cold: a 1 GiB write ahead of every step
+        res["warm_step_ms"] = step_distribution(fn, steps, stream)
+        res["cold_step_ms"] = step_distribution(fn, steps, stream, before=make_flush())
+        torch.cuda.empty_cache()
+    return out, res
 
 
 def probe_copy(nbytes=1 << 30):
@@ -339,6 +390,8 @@ def bench_batched(n_inst, base_seed, steps, warmup, schedules=(2, 1), check=True
         res["per_instance"]["sampled_instances_match_oracle"] = check_sampled(specs, site_off, bond_off, out, idx)
     best = min(res[k]["ms"] for k in res if k.startswith("batched_"))
     res["batched_speedup_vs_per_instance"] = round(ms / best, 3)
+    if check:
+        res["cpu_oracle_threads"] = cpu_oracle_batched(specs)
     del src, dst, occ, out
     torch.cuda.empty_cache()
     return res
@@ -425,6 +478,24 @@ def bench_serving(pool_size, n_req, seed, budget_gb=64.0, slots=8, check=True):
     return res
 
 
+def cpu_oracle_batched(specs, count=256, seed=11):
+    """The oracle's thread pool (one instance per task, all usable host cores)
+    over a seeded sample of the batch's instances, generated on the host."""
+    import gen
+    import oracle
+    u = gen.uniform(seed, gen.STREAM_SPEC, count)
+    pick = sorted({min(int(x * len(specs)), len(specs) - 1) for x in u})
+    sub = [specs[k] for k in pick]
+    site_off, bond_off, src, dst, occ = gen.batch_arrays(sub)
+    threads = host_info()["usable_cpus"] or 1
+    t0 = time.perf_counter()
+    oracle.label_batched(site_off, bond_off, src, dst, occ, n_threads=threads)
+    dt = time.perf_counter() - t0
+    n = int(site_off[-1])
+    return {"value": round(n / dt / 1e9, 5), "unit": "Gsites/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sub)} seeded instances of the batch ({n} sites), {dt:.2f} s"}
+
+
 def cpu_oracle_csr(g):
     import oracle
     t0 = time.perf_counter()
@@ -486,7 +557,9 @@ def main():
              "path_alg_bytes": path_bytes_csr(n, m),
              "path_hbm_GBs": round(path_gbs, 1),
              "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
-             "wall_s_timed": round(r["wall"], 4)}
+             "wall_s_timed": round(r["wall"], 4),
+             "step_ms": r["step_ms"],
+             "host": host_info()}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -503,6 +576,14 @@ def main():
             extra["probe_copy"] = probe_copy()
         except Exception as e:  # measurement aid only
             extra["probe_copy"] = f"failed: {e}"
+        for pp in (0.1736, 0.5209):  # 0.5 p_c and 1.5 p_c of the same lattice
+            gp, outp, rp_ = bench_csr(args.L, pp, args.seed, max(5, args.steps // 2), args.warmup)
+            extra[f"triangle_L{args.L}_p{pp}"] = {
+                "Gsites_s": round(rp_["n"] / (rp_["ms"] * 1e-3) / 1e9, 3),
+                "ms_per_step": round(rp_["ms"], 5), "step_ms": rp_["step_ms"],
+                "kernels": {k: round(v["mean_ms"], 5) for k, v in rp_["kernels"].items()}}
+            del gp, outp
+            torch.cuda.empty_cache()
         h = gen.honeycomb_realization(256, 0.6527, 1)
         _, rh = bench_edges(h, max(args.steps, 50), args.warmup)
         extra["honeycomb_L256"] = {"Gsites_s": round(rh["n"] / (rh["ms"] * 1e-3) / 1e9, 3),
@@ -518,11 +599,12 @@ def main():
             extra["serving"] = f"failed: {type(e).__name__}: {e}"
         for pp in (0.45, 0.5, 0.55):
             b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
-            _, rb = bench_edges(b, args.steps, args.warmup)
+            _, rb = bench_edges(b, args.steps, args.warmup, cold=True)
             gbs = path_bytes_edges(rb["n"], rb["m"]) / (rb["ms"] * 1e-3) / 1e9
             extra[f"random3reg_2^24_p{pp}"] = {
                 "Gsites_s": round(rb["n"] / (rb["ms"] * 1e-3) / 1e9, 3),
                 "ms_per_step": round(rb["ms"], 5), "path_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "warm_step_ms": rb["warm_step_ms"], "cold_step_ms": rb["cold_step_ms"],
                 "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()}}
             del b
 

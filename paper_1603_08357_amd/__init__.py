@@ -134,7 +134,7 @@ def label(src: torch.Tensor, dst: torch.Tensor, n_sites: int, occ: torch.Tensor 
 
 
 def csr_workspace_bytes(n_sites: int, n_bonds: int) -> int:
-    """Workspace ccl_label_csr needs (0 for a graph of one 32768-site tile)."""
+    """Workspace ccl_label_csr needs (0 for a graph of one 65536-site tile)."""
     return int(_lib.ccl_label_csr_workspace_size(n_sites, n_bonds))
 
 

@@ -27,6 +27,7 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
+constexpr int kLdsRounds = 1;  // lockstep pointer-following rounds in LDS
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
 // Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
@@ -52,14 +53,11 @@ __device__ __forceinline__ int4 buf_i32x4(__amdgpu_buffer_rsrc_t r, uint32_t byt
   return make_int4((int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]);
 }
 
-// Tile-relative row of tile-relative bond e in an affine tile of degree d.
-__device__ __forceinline__ int32_t affine_row(int32_t e, int32_t d) {
-  switch (d) {
-    case 1: return e;
-    case 2: return e >> 1;
-    case 3: return e / 3;
-    default: return e >> 2;
-  }
+// Tile-relative row of tile-relative bond e in an affine tile of degree d,
+// as e * ceil(2^20 / d) >> 20 (exact for d <= 4 and e < 2^18, which a tile of
+// 65536 rows of at most 4 bonds satisfies); `magic` is ceil(2^20 / d).
+__device__ __forceinline__ int32_t affine_row(int32_t e, uint32_t magic) {
+  return (int32_t)(((uint64_t)(uint32_t)e * magic) >> 20);
 }
 
 // Join bond (t, v) of the tile (t tile-relative, v global) in LDS, or, when v
@@ -127,6 +125,7 @@ __global__ void __launch_bounds__(kTileBlock)
   const bool affine_try =
       deg >= 1 && deg <= 4 &&
       (!HAS_OCC || ((reinterpret_cast<uintptr_t>(occ + e_begin) & 3) == 0));
+  const uint32_t magic = deg > 0 ? ((1u << 20) + (uint32_t)deg - 1u) / (uint32_t)deg : 0u;
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(row_ptr + lo, (uint32_t)(cnt + 1) * 4u);
   const __amdgpu_buffer_rsrc_t rc = make_rsrc(col + e_begin, fast ? (uint32_t)e_count * 4u : 0u);
   const __amdgpu_buffer_rsrc_t ro =
@@ -172,15 +171,22 @@ __global__ void __launch_bounds__(kTileBlock)
       load(k + 1, 0, cn[0], on[0]);
       load(k + 1, 1, cn[1], on[1]);
       uint32_t leave = 0;  // bit 4u+j: bond j of group u leaves the tile
+      int32_t ja[8], jb[8];  // the lane's bonds inside the tile; (0, 0) for none
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
         const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (((o[u] >> (8 * j)) & 0xFFu) != 0 && tile_bond(par, affine_row(e + j, deg), c4[j], lo, cnt))
-            leave |= 1u << (4 * u + j);
+        for (int j = 0; j < 4; ++j) {
+          const bool on = ((o[u] >> (8 * j)) & 0xFFu) != 0;
+          const uint32_t vl = (uint32_t)c4[j] - (uint32_t)lo;  // lo + cnt <= 2^31
+          const bool inside = vl < (uint32_t)cnt;
+          if (on && !inside) leave |= 1u << (4 * u + j);
+          ja[4 * u + j] = on && inside ? affine_row(e + j, magic) : 0;
+          jb[4 * u + j] = on && inside ? (int32_t)vl : 0;
+        }
       }
+      lds16_unite_lockstep<8, kLdsRounds>(par, ja, jb);
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
@@ -190,7 +196,7 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             if ((leave >> (4 * u + j)) & 1u)
-              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + j, deg)), c4[j]);
+              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + j, magic)), c4[j]);
         }
       }
 #pragma unroll
@@ -205,10 +211,10 @@ __global__ void __launch_bounds__(kTileBlock)
         const int64_t ge = (int64_t)e_begin + x;
         if (HAS_OCC && occ[ge] == 0) continue;
         const int32_t v = col[ge];
-        if (tile_bond(par, affine_row(x, deg), v, lo, cnt)) {
+        if (tile_bond(par, affine_row(x, magic), v, lo, cnt)) {
           const uint32_t sl =
               __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, deg)), v);
+          my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, magic)), v);
         }
       }
     }
@@ -243,12 +249,22 @@ __global__ void __launch_bounds__(kTileBlock)
       }
       uint32_t leave = 0;  // bit kDegFast*k+j: register bond (k, j) leaves the tile
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        const int t = base + k * kTileBlock + tid;
-        if (t >= cnt) continue;
+      for (int h = 0; h < kRowsPerThread; h += 2) {  // two rows' bonds per lockstep join
+        int32_t ja[2 * kDegFast], jb[2 * kDegFast];
 #pragma unroll
-        for (int j = 0; j < kDegFast; ++j)
-          if (ov[k][j] != 0 && tile_bond(par, t, cv[k][j], lo, cnt)) leave |= 1u << (kDegFast * k + j);
+        for (int k = h; k < h + 2; ++k) {
+          const int t = base + k * kTileBlock + tid;
+#pragma unroll
+          for (int j = 0; j < kDegFast; ++j) {
+            const bool on = t < cnt && ov[k][j] != 0;
+            const uint32_t vl = (uint32_t)cv[k][j] - (uint32_t)lo;  // lo + cnt <= 2^31
+            const bool inside = vl < (uint32_t)cnt;
+            if (on && !inside) leave |= 1u << (kDegFast * k + j);
+            ja[kDegFast * (k - h) + j] = on && inside ? t : 0;
+            jb[kDegFast * (k - h) + j] = on && inside ? (int32_t)vl : 0;
+          }
+        }
+        lds16_unite_lockstep<2 * kDegFast, kLdsRounds>(par, ja, jb);
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
@@ -421,7 +437,7 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, 256, 0, s, pairs, seg, label);
   if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
   const unsigned n_win = (unsigned)((n + kFlatWin - 1) / kFlatWin);
-  CCL_LAUNCH("ccl_flatten", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);
+  CCL_LAUNCH("ccl_flatten_window", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);
   return CCL_OK;
 }
 

@@ -284,6 +284,18 @@ __device__ __forceinline__ int32_t lds16_min(uint16_t* par, int32_t x, int32_t v
   }
 }
 
+// Root chase with path halving, given p = par[x] already loaded.
+__device__ __forceinline__ int32_t lds16_find_from(uint16_t* par, int32_t x, int32_t p) {
+  while (p != x) {
+    const int32_t g = lds16_ld(par + p);
+    if (g == p) return p;
+    lds16_st(par + x, g);
+    x = g;
+    p = lds16_ld(par + x);
+  }
+  return x;
+}
+
 __device__ __forceinline__ int32_t lds16_find(uint16_t* par, int32_t x) {
   int32_t p = lds16_ld(par + x);
   while (p != x) {
@@ -308,6 +320,75 @@ __device__ __forceinline__ void lds16_unite(uint16_t* par, int32_t a, int32_t b)
     const int32_t old = lds16_min(par, r1, r2);
     if (old == r2 || old == r1) break;
     r1 = old;
+  }
+}
+
+// Step (iii) in LDS for P bonds of a lane at once (tile-relative ends; a
+// bond with a[k] == b[k] does nothing): the first parent loads of all 2P ends
+// are issued together, then ROUNDS pointer-following rounds in which every
+// end steps (a root steps onto itself), then the rare longer chases one by
+// one.  Algorithm 1's minimum is then taken for all P bonds together: one
+// word load and at most one compare-and-swap each, the few that lose a race
+// retrying through lds16_min, and the join loop continuing only where the
+// higher root was no longer a root.
+template <int P, int ROUNDS>
+__device__ __forceinline__ void lds16_unite_lockstep(uint16_t* par, int32_t (&a)[P], int32_t (&b)[P]) {
+  int32_t pa[P], pb[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    pa[k] = lds16_ld(par + a[k]);
+    pb[k] = lds16_ld(par + b[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      a[k] = pa[k];
+      b[k] = pb[k];
+      pa[k] = lds16_ld(par + a[k]);
+      pb[k] = lds16_ld(par + b[k]);
+    }
+  }
+  int32_t hi[P], lo[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    if (pa[k] != a[k]) a[k] = lds16_find_from(par, a[k], pa[k]);
+    if (pb[k] != b[k]) b[k] = lds16_find_from(par, b[k], pb[k]);
+    hi[k] = max(a[k], b[k]);
+    lo[k] = min(a[k], b[k]);
+  }
+  uint32_t* w32 = reinterpret_cast<uint32_t*>(par);
+  uint32_t w[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    w[k] = __hip_atomic_load(w32 + (hi[k] >> 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  int32_t old[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const uint32_t sh = (uint32_t)(hi[k] & 1) * 16u;
+    old[k] = (int32_t)((w[k] >> sh) & 0xFFFFu);
+    if (old[k] > lo[k]) {  // implies hi != lo
+      uint32_t seen = w[k];
+      const uint32_t next = (w[k] & ~(0xFFFFu << sh)) | ((uint32_t)lo[k] << sh);
+      if (!__hip_atomic_compare_exchange_strong(w32 + (hi[k] >> 1), &seen, next, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        old[k] = lds16_min(par, hi[k], lo[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    int32_t r1 = old[k], r2 = lo[k];
+    if (r1 == r2 || r1 == hi[k]) continue;
+    while (r1 != r2) {
+      if (r1 < r2) {
+        const int32_t t = r1;
+        r1 = r2;
+        r2 = t;
+      }
+      const int32_t o = lds16_min(par, r1, r2);
+      if (o == r2 || o == r1) break;
+      r1 = o;
+    }
   }
 }
 

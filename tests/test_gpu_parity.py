@@ -320,10 +320,13 @@ def test_argument_errors(ccl):
     e = dev(np.zeros(4, np.int32))
     with pytest.raises(ccl.CclError):  # labels alias an input
         ccl.label(e, e, 4, out=e)
-    g = gen.triangle_csr_realization(200, 0.3, 1)
-    with pytest.raises(ccl.CclError):  # workspace too small for 40000 sites
+    g = gen.triangle_csr_realization(300, 0.3, 1)
+    assert ccl.csr_workspace_bytes(g.n_sites, len(g.col)) > 8  # 90000 sites: two tiles
+    with pytest.raises(ccl.CclError):  # workspace too small
         ccl.label_csr(dev(g.row_ptr), dev(g.col), dev(g.occ),
                       workspace=torch.empty(8, dtype=torch.uint8, device="cuda"))
+    small = gen.triangle_csr_realization(200, 0.3, 1)  # one tile: no workspace needed
+    assert ccl.csr_workspace_bytes(small.n_sites, len(small.col)) == 0
 
 
 # ------------------------------------------------------------ serving & autotune
