@@ -118,10 +118,11 @@ typedef struct {
   int32_t blocks_per_cu;   /* resident workgroups per compute unit */
   int32_t bonds_per_chunk; /* bonds in one merge work item */
   int32_t sites_per_chunk; /* sites in one init / flatten work item */
-  int32_t small_sites;     /* instances up to this many sites are labelled
-                              entirely in LDS by one workgroup; 0 = default
-                              (fits the LDS of the resident workgroups),
-                              negative = never */
+  int32_t small_sites;     /* instances up to this many sites (<= 65536) are
+                              labelled entirely in LDS by one workgroup, two
+                              bytes of LDS per site; 0 = default (fits the
+                              LDS of the resident workgroups), negative =
+                              never */
   int32_t schedule;        /* 1 = fused: one persistent launch in which work
                               items wait for the items they depend on;
                               2 = phased: init, merge and flatten items as

@@ -73,7 +73,7 @@ def candidates(space=None, limit=None):
     out = []
     for vals in itertools.product(*(space[k] for k in keys)):
         t = dict(zip(keys, vals))
-        lds = max(t["small_sites"], 0) * 4  # explicit sizes only; 0 = library default
+        lds = (max(t["small_sites"], 0) + 1) // 2 * 4  # 16-bit parents; 0 = library default
         if lds * t["blocks_per_cu"] > 160 * 1024:
             continue
         out.append(t)

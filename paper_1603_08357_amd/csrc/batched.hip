@@ -3,8 +3,8 @@
 // Each instance runs the three steps of section 3 -- init (i), the Algorithm 1
 // merge over its occupied bonds (iii), flatten (iv) -- split into work items:
 //   SMALL     an instance of at most `small_sites` sites, labelled entirely in
-//             LDS by one workgroup (init, merge and flatten on the LDS copy,
-//             then one coalesced store);
+//             LDS by one workgroup (init, merge and flatten on a 16-bit LDS
+//             parent array, then one coalesced store);
 //   INIT c    sites [c*S, (c+1)*S) of a large instance;
 //   MERGE c   bonds [c*Bc, (c+1)*Bc), after every INIT item of the instance;
 //   FLATTEN c sites [c*S, ...), after every MERGE item of the instance.
@@ -75,42 +75,6 @@ __device__ __forceinline__ void raise_error(uint32_t* error, uint32_t bit) {
   __hip_atomic_fetch_or(error, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root chase that refuses invalid labels: a valid label never points upward
-// (label[x] <= x), so a chain strictly decreases and stays in [0, n).
-__device__ __forceinline__ int32_t find_root_checked(const int32_t* lab, int32_t x, bool& bad) {
-  int32_t p = lab_ld(lab + x);
-  while (p != x) {
-    if (p > x || p < 0) {
-      bad = true;
-      return x;
-    }
-    x = p;
-    p = lab_ld(lab + x);
-  }
-  return x;
-}
-
-// Algorithm 1 with the same refusal: a returned old value above r1 or below
-// zero cannot come from a valid forest.
-__device__ __forceinline__ void unite_checked(int32_t* lab, int32_t a, int32_t b, bool& bad) {
-  int32_t r1 = find_root_halving_checked(lab, a, lab_ld(lab + a), bad);
-  int32_t r2 = find_root_halving_checked(lab, b, lab_ld(lab + b), bad);
-  while (!bad && r1 != r2) {
-    if (r1 < r2) {
-      int32_t t = r1;
-      r1 = r2;
-      r2 = t;
-    }
-    const int32_t old = lab_min(lab + r1, r2);
-    if (old == r2 || old == r1) break;
-    if (old > r1 || old < 0) {
-      bad = true;
-      break;
-    }
-    r1 = old;
-  }
-}
-
 // Fused schedule: thread 0 waits for *ctr >= need; returns false (for the
 // whole workgroup) when it gave up or the launch already failed.
 __device__ bool wait_count(const BatchArgs& a, int32_t* ctr, int32_t need, uint32_t* ok_slot) {
@@ -178,12 +142,28 @@ __global__ void k_batched(BatchArgs a) {
     bool bad = false;
 
     if (kind == kItemSmall) {
-      for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = i;
+      // 16-bit parents (the instance has at most 65536 sites), kLockstep
+      // bonds per lane joined in lockstep; (0, 0) is the no-op bond
+      uint16_t* par = reinterpret_cast<uint16_t*>(lds);
+      for (int32_t w = threadIdx.x; 2 * w < n; w += blockDim.x)
+        reinterpret_cast<uint32_t*>(par)[w] = (uint32_t)(2 * w) | ((uint32_t)(2 * w + 1) << 16);
       __syncthreads();
-      for (int64_t b = threadIdx.x; b < m; b += blockDim.x)
-        if (occ == nullptr || occ[b] != 0) lds_unite(lds, src[b], dst[b]);
+      const int64_t step = (int64_t)kLockstep * blockDim.x;
+      for (int64_t b0 = 0; b0 < m; b0 += step) {
+        int32_t u[kLockstep], v[kLockstep];
+#pragma unroll
+        for (int k = 0; k < kLockstep; ++k) {
+          const int64_t b = b0 + (int64_t)k * blockDim.x + threadIdx.x;
+          const int64_t bc = b < m ? b : 0;  // clamped: loads stay unconditional
+          const bool on = b < m && (occ == nullptr || occ[bc] != 0);
+          const int32_t x = src[bc], y = dst[bc];
+          u[k] = on ? x : 0;
+          v[k] = on ? y : 0;
+        }
+        lds16_unite_lockstep<kLockstep, 2>(par, u, v);
+      }
       __syncthreads();
-      for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lab[i] = lds_find(lds, i);
+      for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lab[i] = lds16_find(par, i);
     } else if (kind == kItemInit) {
       const int32_t lo = c * a.sites_per_chunk;
       const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
@@ -220,20 +200,64 @@ __global__ void k_batched(BatchArgs a) {
         const int32_t lo = c * a.sites_per_chunk;
         const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
         // only roots are stored (see the flatten of the single-instance
-        // path): the site's own root, and the root into the site's parent
-        for (int32_t i = lo + threadIdx.x; i < hi && !bad; i += blockDim.x) {
-          const int32_t p = lab_ld(lab + i);
-          if (p == i) continue;
-          if (p > i || p < 0) {
-            bad = true;
-            break;
+        // path): the site's own root, and the root into the site's parent.
+        // kLockstep sites per lane: their labels and their parents' labels
+        // are read together, then the remaining chases advance one link per
+        // round while any lane of the wavefront has one.
+        constexpr int K = kLockstep;
+        for (int32_t i0 = lo; i0 < hi; i0 += K * (int32_t)blockDim.x) {
+          int32_t p[K], q[K], x[K], px[K];
+          bool need[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int32_t i = i0 + k * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+            p[k] = lab_ld(lab + (i < hi ? i : lo));
           }
-          const int32_t q = lab_ld(lab + p);
-          if (q == p) continue;
-          const int32_t r = find_root_checked(lab, q, bad);
-          if (bad) break;
-          if (r != q) lab_st(lab + p, r);
-          lab_st(lab + i, r);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int32_t i = i0 + k * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+            bool in = i < hi && p[k] != i;
+            if (in && (p[k] > i || p[k] < 0)) {
+              bad = true;
+              in = false;
+            }
+            q[k] = lab_ld(lab + (in ? p[k] : 0));
+            if (in && (q[k] > p[k] || q[k] < 0)) {
+              bad = true;
+              in = false;
+            }
+            need[k] = in && q[k] != p[k];
+            x[k] = q[k];
+            px[k] = lab_ld(lab + (need[k] ? x[k] : 0));
+          }
+          for (;;) {
+            bool open = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              if (need[k] && (px[k] > x[k] || px[k] < 0)) {
+                bad = true;
+                need[k] = false;
+              }
+              open = open || (need[k] && px[k] != x[k]);
+            }
+            if (!__any(open)) break;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              // unconditional load (index 0 when idle); an idle chase keeps its value
+              const bool go = need[k] && px[k] != x[k];
+              x[k] = go ? px[k] : x[k];
+              const int32_t nx = lab_ld(lab + (go ? x[k] : 0));
+              px[k] = go ? nx : px[k];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (!need[k]) continue;
+            const int32_t i = i0 + k * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+            if (x[k] != q[k]) lab_st(lab + p[k], x[k]);
+            lab_st(lab + i, x[k]);
+          }
+          if (__any(bad)) break;
         }
       }
     }
@@ -275,19 +299,26 @@ static ccl_tuning resolve_tuning(const ccl_tuning* t, const DeviceInfo& d) {
   if (r.small_sites < 0) {
     r.small_sites = 0;  // LDS path off
   } else if (r.small_sites == 0) {
-    // one small instance per resident workgroup must fit the CU's LDS
-    const int cap = (160 * 1024) / r.blocks_per_cu / 4 - 64;
-    r.small_sites = std::min(cap, std::min(8192, d.max_lds_per_block / 4 - 64));
+    // one small instance per resident workgroup must fit the CU's LDS (two
+    // bytes per site)
+    const int cap = (160 * 1024) / r.blocks_per_cu / 2 - 128;
+    r.small_sites = std::min(cap, std::min(16384, d.max_lds_per_block / 2 - 128));
   }
   if (r.schedule == kScheduleDefault) r.schedule = kSchedulePhased;
   return r;
 }
 
+// LDS a SMALL item takes: 16-bit parents, whole 32-bit words
+static int64_t small_lds_bytes(const ccl_tuning& t) {
+  return ((int64_t)std::max(t.small_sites, 0) + 1) / 2 * 4;
+}
+
 static bool tuning_ok(const ccl_tuning& t, const DeviceInfo& d) {
   if (t.block_threads % 64 != 0 || t.block_threads > 1024) return false;
   if (t.blocks_per_cu > 32 || t.bonds_per_chunk <= 0 || t.sites_per_chunk <= 0) return false;
-  if ((int64_t)t.small_sites * 4 + 64 > d.max_lds_per_block) return false;
-  if (((int64_t)t.small_sites * 4 + 64) * t.blocks_per_cu > 160 * 1024) return false;
+  if (t.small_sites > 65536) return false;  // 16-bit LDS parents
+  if (small_lds_bytes(t) + 64 > d.max_lds_per_block) return false;
+  if ((small_lds_bytes(t) + 64) * t.blocks_per_cu > 160 * 1024) return false;
   if (t.schedule != kScheduleFused && t.schedule != kSchedulePhased) return false;
   return true;
 }
@@ -461,7 +492,7 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
   a.bonds_per_chunk = plan->tuning.bonds_per_chunk;
   a.spin_limit = 1u << 20;
   a.fused = fused ? 1 : 0;
-  const unsigned lds = (unsigned)plan->tuning.small_sites * 4;
+  const unsigned lds = (unsigned)small_lds_bytes(plan->tuning);
   if (fused) {
     a.items = plan->d_items;
     a.n_items = plan->n_items;

@@ -27,7 +27,7 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
-constexpr int kLdsRounds = 1;  // lockstep pointer-following rounds in LDS
+constexpr int kLdsRounds = 2;  // unconditional chase rounds before the voted ones
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
 // Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
@@ -249,22 +249,19 @@ __global__ void __launch_bounds__(kTileBlock)
       }
       uint32_t leave = 0;  // bit kDegFast*k+j: register bond (k, j) leaves the tile
 #pragma unroll
-      for (int h = 0; h < kRowsPerThread; h += 2) {  // two rows' bonds per lockstep join
-        int32_t ja[2 * kDegFast], jb[2 * kDegFast];
+      for (int k = 0; k < kRowsPerThread; ++k) {  // one row's bonds per lockstep join
+        int32_t ja[kDegFast], jb[kDegFast];
+        const int t = base + k * kTileBlock + tid;
 #pragma unroll
-        for (int k = h; k < h + 2; ++k) {
-          const int t = base + k * kTileBlock + tid;
-#pragma unroll
-          for (int j = 0; j < kDegFast; ++j) {
-            const bool on = t < cnt && ov[k][j] != 0;
-            const uint32_t vl = (uint32_t)cv[k][j] - (uint32_t)lo;  // lo + cnt <= 2^31
-            const bool inside = vl < (uint32_t)cnt;
-            if (on && !inside) leave |= 1u << (kDegFast * k + j);
-            ja[kDegFast * (k - h) + j] = on && inside ? t : 0;
-            jb[kDegFast * (k - h) + j] = on && inside ? (int32_t)vl : 0;
-          }
+        for (int j = 0; j < kDegFast; ++j) {
+          const bool on = t < cnt && ov[k][j] != 0;
+          const uint32_t vl = (uint32_t)cv[k][j] - (uint32_t)lo;  // lo + cnt <= 2^31
+          const bool inside = vl < (uint32_t)cnt;
+          if (on && !inside) leave |= 1u << (kDegFast * k + j);
+          ja[j] = on && inside ? t : 0;
+          jb[j] = on && inside ? (int32_t)vl : 0;
         }
-        lds16_unite_lockstep<2 * kDegFast, kLdsRounds>(par, ja, jb);
+        lds16_unite_lockstep<kDegFast, kLdsRounds>(par, ja, jb);
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
@@ -305,65 +302,131 @@ __global__ void __launch_bounds__(kTileBlock)
 
 // Cross kernel: one workgroup per tile (tiles renumbered so that each XCD
 // takes a contiguous range of them and its L2 holds the neighbouring tiles
-// those joins touch).  A lane carries kPairsInFlight leaving bonds through the
-// join in lockstep: the first parents of all their ends are requested
-// together, each chase round advances every unfinished chase by one link,
-// and the first atomicMin of every join is issued back to back.  Joins whose
-// atomicMin displaced a link finish with the sequential loop.  Interleaving
-// the joins of one lane is just one more schedule of Algorithm 1, which is
-// correct under any interleaving.
-constexpr int kPairsInFlight = 8;
-constexpr int kChaseRounds = 4;
+// those joins touch) walks the tile's leaving-bond pairs in chunks.  Before
+// anything touches global atomics, a chunk is reduced in LDS:
+//   1. every pair (u, v) is replaced by (label[u], label[v]) -- after the
+//      tile kernel these are tile-local roots, so many pairs coincide (a
+//      cluster crosses a tile boundary at many bonds);
+//   2. those labels are entered in a hash table (open addressing; a chunk of
+//      kCrossChunk pairs has at most 2 kCrossChunk distinct labels, so the
+//      table of kCrossSlots never fills), and the pairs are joined there with
+//      the LDS union-find on slot numbers;
+//   3. every table entry that is not the root of its local component issues
+//      one global join, Algorithm 1 in global memory, with the label at the
+//      component's root slot.
+// The global joins are a spanning forest of the chunk's pairs, so the result
+// is the same connectivity with far fewer global chases and atomics: above
+// the threshold, where nearly every leaving bond belongs to the spanning
+// cluster, a chunk reduces to a handful of joins instead of thousands of
+// atomics on the same few addresses.
+constexpr int kCrossBlock = 256;
+constexpr int kCrossPer = 8;  // pairs (and later joins) a lane carries in lockstep
+constexpr int kCrossJoinPer = 4;  // global joins a lane carries in lockstep
+constexpr int kCrossChunk = kCrossPer * kCrossBlock;
+constexpr int kCrossSlots = 2 * kCrossChunk;
+constexpr int32_t kEmpty = -1;
+static_assert((kCrossSlots & (kCrossSlots - 1)) == 0 && kCrossSlots <= 65536, "slot ids are 16-bit");
 
-__global__ void __launch_bounds__(256)
+// Table slots of the 2P labels a lane holds, inserting the absent ones:
+// linear probing in lockstep, one compare-and-swap per label per round (a
+// label already placed re-tries its own slot, which fails harmlessly), until
+// every label of the wavefront has its slot.
+template <int P>
+__device__ __forceinline__ void slots_of(int32_t* keys, int32_t (&a)[P], int32_t (&b)[P]) {
+  constexpr int kBits = __builtin_ctz(kCrossSlots);
+  int32_t ka[P], kb[P];
+  uint32_t open = 0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    ka[k] = a[k];
+    kb[k] = b[k];
+    a[k] = (int32_t)(((uint32_t)ka[k] * 0x9E3779B1u) >> (32 - kBits));
+    b[k] = (int32_t)(((uint32_t)kb[k] * 0x9E3779B1u) >> (32 - kBits));
+  }
+  open = (1u << (2 * P)) - 1u;
+  while (__any(open != 0)) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      int32_t sa = kEmpty, sb = kEmpty;
+      __hip_atomic_compare_exchange_strong(keys + a[k], &sa, ka[k], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_compare_exchange_strong(keys + b[k], &sb, kb[k], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      if ((open >> k) & 1u) {
+        if (sa == kEmpty || sa == ka[k])
+          open &= ~(1u << k);
+        else
+          a[k] = (a[k] + 1) & (kCrossSlots - 1);
+      }
+      if ((open >> (P + k)) & 1u) {
+        if (sb == kEmpty || sb == kb[k])
+          open &= ~(1u << (P + k));
+        else
+          b[k] = (b[k] + 1) & (kCrossSlots - 1);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kCrossBlock)
     k_csr_cross(const int2* __restrict__ pairs, const int2* __restrict__ seg, int32_t* label) {
+  __shared__ int32_t keys[kCrossSlots];
+  __shared__ uint16_t lpar[kCrossSlots];
+  constexpr int P = kCrossPer;
+  const int tid = threadIdx.x;
   const uint32_t tile = xcd_block_id();
   const int2 sc = seg[tile];
   const int2* p = pairs + sc.x;
   const int32_t count = sc.y;
-  constexpr int P = kPairsInFlight;
-  for (int32_t i0 = P * threadIdx.x; i0 < count; i0 += P * 256) {
-    int32_t a[P], b[P], pa[P], pb[P];
+  bool unused = false;
+  for (int32_t c0 = 0; c0 < count; c0 += kCrossChunk) {
+    for (int s = tid; s < kCrossSlots; s += kCrossBlock) keys[s] = kEmpty;
+    for (int w = tid; w < kCrossSlots / 2; w += kCrossBlock)
+      reinterpret_cast<uint32_t*>(lpar)[w] = (uint32_t)(2 * w) | ((uint32_t)(2 * w + 1) << 16);
+    __syncthreads();
+    // 1. the chunk's pairs and their current labels (clamped loads: pairs past
+    //    the end repeat the last one and are dropped below)
+    int32_t a[P], b[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      // clamped index: every load is issued unconditionally (no branch, no
-      // wait between them); pairs past the end become (0, 0), a no-op
-      const int2 e = p[min(i0 + k, count - 1)];
-      const bool in = i0 + k < count;
-      a[k] = in ? e.x : 0;
-      b[k] = in ? e.y : 0;
+      const int2 e = p[min(c0 + k * kCrossBlock + tid, count - 1)];
+      a[k] = e.x;
+      b[k] = e.y;
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      pa[k] = lab_ld(label + a[k]);
-      pb[k] = lab_ld(label + b[k]);
+      a[k] = lab_ld(label + a[k]);
+      b[k] = lab_ld(label + b[k]);
     }
-    // lockstep chase: after round r every chase of length <= r + 1 is done
+    // 2. table slots, joined in LDS (labels of pairs past the end are
+    //    entered too, harmlessly: they repeat the chunk's last pair)
+    bool in[P];
 #pragma unroll
-    for (int r = 0; r < kChaseRounds; ++r) {
+    for (int k = 0; k < P; ++k) in[k] = c0 + k * kCrossBlock + tid < count && a[k] != b[k];
+    slots_of<P>(keys, a, b);
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        // branch-free: a finished chase re-reads its root (a cache hit)
-        a[k] = pa[k];
-        b[k] = pb[k];
-        pa[k] = lab_ld(label + a[k]);
-        pb[k] = lab_ld(label + b[k]);
+    for (int k = 0; k < P; ++k) {
+      a[k] = in[k] ? a[k] : 0;
+      b[k] = in[k] ? b[k] : 0;
+    }
+    lds16_unite_lockstep<P, 1>(lpar, a, b);
+    __syncthreads();
+    // 3. one global join per entry below its local root, kCrossJoinPer per
+    //    lane in lockstep
+    constexpr int J = kCrossJoinPer;
+    for (int s0 = 0; s0 < kCrossSlots; s0 += J * kCrossBlock) {
+      int32_t x[J], y[J];
+#pragma unroll
+      for (int k = 0; k < J; ++k) {
+        const int s = s0 + k * kCrossBlock + tid;
+        const int32_t key = keys[s];
+        const int32_t r = key != kEmpty ? lds16_find(lpar, s) : s;
+        x[k] = r != s ? key : 0;
+        y[k] = r != s ? keys[r] : 0;
       }
+      unite_lockstep<J, 2, false>(label, x, y, unused);
     }
-    int32_t hi[P], lo[P], old[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      // longer chases finish sequentially, with path halving
-      if (pa[k] != a[k]) a[k] = find_root_halving_from(label, a[k], pa[k]);
-      if (pb[k] != b[k]) b[k] = find_root_halving_from(label, b[k], pb[k]);
-      hi[k] = max(a[k], b[k]);
-      lo[k] = min(a[k], b[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < P; ++k) old[k] = hi[k] != lo[k] ? lab_min(label + hi[k], lo[k]) : lo[k];
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-      if (old[k] != lo[k] && old[k] != hi[k]) join_roots(label, old[k], lo[k]);
+    __syncthreads();  // the table is reset for the next chunk
   }
 }
 
@@ -377,6 +440,7 @@ __global__ void __launch_bounds__(256)
 // 16-byte stores.  Windows are renumbered so each XCD takes a contiguous run.
 constexpr int kFlatWin = 32768;
 constexpr int kFlatBlock = 1024;
+constexpr int kFlatPer = 8;  // sites a lane resolves in lockstep
 
 __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, int64_t n) {
   __shared__ int32_t w[kFlatWin];
@@ -388,19 +452,58 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, i
   for (int32_t t = tid; t < cnt4; t += kFlatBlock) reinterpret_cast<int4*>(w)[t] = src4[t];
   for (int32_t t = 4 * cnt4 + tid; t < cnt; t += kFlatBlock) w[t] = label[w0 + t];
   __syncthreads();
-  for (int32_t t = tid; t < cnt; t += kFlatBlock) {
-    const int32_t p = lds_ld(w + t);
-    if (p == (int32_t)(w0 + t)) continue;  // a root
-    const int64_t pl = (int64_t)p - w0;
-    const bool inside = pl >= 0 && pl < cnt;
-    const int32_t q = inside ? lds_ld(w + pl) : lab_ld(label + p);
-    if (q == p) continue;  // the parent is a root: already final
-    const int32_t r = find_root(label, q);
-    if (inside)
-      lds_st(w + pl, r);  // the parent's final root, for the threads sharing it
-    else if (r != q)
-      lab_st(label + p, r);
-    lds_st(w + t, r);
+  // kFlatPer sites per lane in lockstep: their parents' labels are read
+  // together (from the window when the parent lies inside it, else from
+  // global memory), then the chases that remain advance one link per round,
+  // all of them at once, while any lane of the wavefront still has one
+  constexpr int K = kFlatPer;
+  for (int32_t t0 = 0; t0 < cnt; t0 += K * kFlatBlock) {
+    int32_t p[K], q[K], x[K], px[K];
+    uint32_t pin[K];
+    bool need[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) p[k] = lds_ld(w + min(t0 + k * kFlatBlock + tid, cnt - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      pin[k] = (uint32_t)((int64_t)p[k] - w0);  // parent's window slot (>= cnt: outside)
+      const bool inside = pin[k] < (uint32_t)cnt;
+      const int32_t ql = lds_ld(w + (inside ? pin[k] : 0u));
+      const int32_t qg = lab_ld(label + (inside ? 0 : p[k]));
+      q[k] = inside ? ql : qg;  // the parent's label
+      x[k] = q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t t = t0 + k * kFlatBlock + tid;
+      // a root, or a site whose parent is a root, is final already
+      need[k] = t < cnt && p[k] != (int32_t)(w0 + t) && x[k] != p[k];
+      px[k] = lab_ld(label + (need[k] ? x[k] : 0));
+    }
+    for (;;) {
+      bool open = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) open = open || (need[k] && px[k] != x[k]);
+      if (!__any(open)) break;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        // the load is unconditional (index 0 when idle); an idle chase keeps
+        // its value
+        const bool go = need[k] && px[k] != x[k];
+        x[k] = go ? px[k] : x[k];
+        const int32_t nx = lab_ld(label + (go ? x[k] : 0));
+        px[k] = go ? nx : px[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!need[k]) continue;
+      const int32_t t = t0 + k * kFlatBlock + tid;
+      if (pin[k] < (uint32_t)cnt)
+        lds_st(w + pin[k], x[k]);  // the parent's final root, for the sites sharing it
+      else if (x[k] != q[k])
+        lab_st(label + p[k], x[k]);
+      lds_st(w + t, x[k]);
+    }
   }
   __syncthreads();
   int4* dst4 = reinterpret_cast<int4*>(label + w0);
@@ -434,7 +537,7 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<false>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
                col, occ, label, pairs, seg);
   if (n_tiles == 1) return CCL_OK;
-  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, 256, 0, s, pairs, seg, label);
+  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, kCrossBlock, 0, s, pairs, seg, label);
   if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
   const unsigned n_win = (unsigned)((n + kFlatWin - 1) / kFlatWin);
   CCL_LAUNCH("ccl_flatten_window", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);

@@ -114,6 +114,41 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
         q[j][t] = need ? got : c[t];
       }
     }
+    // chases that remain (the parent is not a root) advance one link per
+    // round, all sixteen at once, while any lane of the wavefront has one
+    int32_t x[G][4], px[G][4];
+    uint32_t open = 0;  // bit 4j+t: site t of group j is still chasing
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int64_t g = gb + j * kBlock + threadIdx.x;
+      const int32_t* c = reinterpret_cast<const int32_t*>(&v[j]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool need = g < g1 && g < full && c[t] != (int32_t)((g << 2) + t) && q[j][t] != c[t];
+        open |= (uint32_t)need << (4 * j + t);
+        x[j][t] = q[j][t];
+        px[j][t] = lab_ld(label + (need ? x[j][t] : 0));
+      }
+    }
+    const uint32_t needed = open;
+    for (;;) {
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (px[j][t] == x[j][t]) open &= ~(1u << (4 * j + t));
+      if (!__any(open != 0)) break;
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          // unconditional load (index 0 when idle); an idle chase keeps its value
+          const bool go = (open >> (4 * j + t)) & 1u;
+          x[j][t] = go ? px[j][t] : x[j][t];
+          const int32_t nx = lab_ld(label + (go ? x[j][t] : 0));
+          px[j][t] = go ? nx : px[j][t];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const int64_t g = gb + j * kBlock + threadIdx.x;
@@ -121,17 +156,15 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
       const int64_t i0 = g << 2;
       if (g < full) {
         int32_t* c = reinterpret_cast<int32_t*>(&v[j]);
-        bool changed = false;
+        if ((needed >> (4 * j)) & 0xFu) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int32_t p = c[t];
-          if (p == (int32_t)(i0 + t) || q[j][t] == p) continue;
-          const int32_t r = find_root(label, q[j][t]);
-          if (r != q[j][t]) lab_st(label + p, r);
-          c[t] = r;
-          changed = true;
+          for (int t = 0; t < 4; ++t) {
+            if (!((needed >> (4 * j + t)) & 1u)) continue;
+            if (x[j][t] != q[j][t]) lab_st(label + c[t], x[j][t]);  // the parent's root
+            c[t] = x[j][t];
+          }
+          reinterpret_cast<int4*>(label)[g] = v[j];
         }
-        if (changed) reinterpret_cast<int4*>(label)[g] = v[j];
       } else {
         for (int64_t i = i0; i < min(i0 + 4, n); ++i) {
           const int32_t p = lab_ld(label + i);

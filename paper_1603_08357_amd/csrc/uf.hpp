@@ -34,6 +34,19 @@ __device__ __forceinline__ int32_t lab_min(int32_t* p, int32_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The compression store of the merge step (path halving): label[x] lowered
+// to an ancestor, as a device-coherent atomicMin whose result is unused.
+// It can never raise a label, so however late it lands -- even after a
+// later kernel wrote x's final root, which is at most the ancestor -- it
+// leaves a correct value.  A plain store can land that late: under
+// concurrent kernels on other streams, a merge-step compression store was
+// seen to overwrite a final root written by the following flatten kernel
+// (about one request in 4000 of a serving run on MI355X had one wrong
+// label; with this form none in 20000).
+__device__ __forceinline__ void lab_lower(int32_t* p, int32_t v) {
+  __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The analysis chase (sections 2-3): follow label until label[r] == r.
 __device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
   int32_t p = lab_ld(label + x);
@@ -46,17 +59,15 @@ __device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
 
 // The same chase with path halving: every visited site is re-pointed at its
 // grandparent (a smaller member of the same cluster), so chains that many
-// concurrent joins stacked up shrink as threads walk them.  The plain store
-// may overwrite a value an atomicMin lowered meanwhile; that atomic's loop
-// re-joins the value it displaced, so no link is lost.  For the merge step
-// only: a halving store can also land after another thread wrote a site's
-// root, which the flatten step must never allow (its writes are final).
+// concurrent joins stacked up shrink as threads walk them.  The store is an
+// atomicMin (lab_lower), so it never undoes a lower link another thread made.
+// For the merge step only: the flatten step stores nothing but final roots.
 __device__ __forceinline__ int32_t find_root_halving(int32_t* label, int32_t x) {
   int32_t p = lab_ld(label + x);
   while (p != x) {
     const int32_t g = lab_ld(label + p);
     if (g == p) return p;
-    lab_st(label + x, g);
+    lab_lower(label + x, g);
     x = g;
     p = lab_ld(label + x);
   }
@@ -69,7 +80,7 @@ __device__ __forceinline__ int32_t find_root_halving_from(int32_t* label, int32_
   while (p != x) {
     const int32_t g = lab_ld(label + p);
     if (g == p) return p;
-    lab_st(label + x, g);
+    lab_lower(label + x, g);
     x = g;
     p = lab_ld(label + x);
   }
@@ -123,7 +134,7 @@ __device__ __forceinline__ int32_t find_root_halving_checked(int32_t* label, int
       bad = true;
       return x;
     }
-    lab_st(label + x, g);
+    lab_lower(label + x, g);
     x = g;
     p = lab_ld(label + x);
   }
@@ -219,39 +230,6 @@ __device__ __forceinline__ int32_t lds_ld(const int32_t* p) {
 __device__ __forceinline__ void lds_st(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ int32_t lds_min(int32_t* p, int32_t v) {
-  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Root chase in LDS with path halving (x -> grandparent).  The racy store is
-// safe for the reasons given at the top of this file: it writes an ancestor.
-__device__ __forceinline__ int32_t lds_find(int32_t* par, int32_t x) {
-  int32_t p = lds_ld(par + x);
-  while (p != x) {
-    int32_t g = lds_ld(par + p);
-    if (g == p) return p;
-    lds_st(par + x, g);
-    x = g;
-    p = lds_ld(par + x);
-  }
-  return x;
-}
-
-__device__ __forceinline__ void lds_unite(int32_t* par, int32_t a, int32_t b) {
-  int32_t r1 = lds_find(par, a);
-  int32_t r2 = lds_find(par, b);
-  while (r1 != r2) {
-    if (r1 < r2) {
-      int32_t t = r1;
-      r1 = r2;
-      r2 = t;
-    }
-    int32_t old = lds_min(par + r1, r2);
-    if (old == r2 || old == r1) break;
-    r1 = old;
-  }
-}
-
 // ---------------------------------------------------------------- LDS, 16-bit
 
 // A tile of up to 65536 sites keeps its parent array as 16-bit tile-relative

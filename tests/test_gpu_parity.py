@@ -378,3 +378,47 @@ def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
     out = plan.label(dev(src), dev(dst), dev(occ))
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), want)
+# ------------------------------------------------------------ concurrency
+
+def test_concurrent_streams_match_oracle(ccl):
+    """Edge-list and CSR jobs in flight on eight streams at once: every
+    result equals the oracle's.  (A merge-step compression store landing
+    after the flatten's final root store showed up only under concurrent
+    kernels; compression stores are atomicMin for that reason.)"""
+    rng_graphs = []
+    for i, (n, z, p) in enumerate([(300_000, 3, 0.5), (200_000, 4, 0.33), (150_000, 6, 0.2)]):
+        g = gen.bethe_random_regular(n, z, p, 40 + i)
+        rng_graphs.append(("edges", g, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)))
+    for L, p in [(300, 0.3473), (512, 0.5209)]:
+        g = gen.triangle_csr_realization(L, p, L)
+        rng_graphs.append(("csr", g, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)))
+    S = 8
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    bufs = []
+    for kind, g, _ in rng_graphs:
+        if kind == "edges":
+            ins = (dev(g.src), dev(g.dst), dev(g.occ))
+            ws = None
+        else:
+            ins = (dev(g.row_ptr), dev(g.col), dev(g.occ))
+            ws = [torch.empty(max(ccl.csr_workspace_bytes(g.n_sites, len(g.col)), 8), dtype=torch.uint8,
+                              device="cuda") for _ in range(S)]
+        outs = [torch.empty(g.n_sites, dtype=torch.int32, device="cuda") for _ in range(S)]
+        bufs.append((ins, ws, outs))
+    torch.cuda.synchronize()
+    _say(f"concurrent: {len(rng_graphs)} graphs x {S} streams")
+    for it in range(40):
+        picks = []
+        for s in range(S):
+            gi = (it + s) % len(rng_graphs)
+            kind, g, _ = rng_graphs[gi]
+            ins, ws, outs = bufs[gi]
+            with torch.cuda.stream(streams[s]):
+                if kind == "edges":
+                    ccl.label(ins[0], ins[1], g.n_sites, ins[2], out=outs[s], stream=streams[s])
+                else:
+                    ccl.label_csr(ins[0], ins[1], ins[2], out=outs[s], workspace=ws[s], stream=streams[s])
+            picks.append((s, gi))
+        for s, gi in picks:
+            streams[s].synchronize()
+            np.testing.assert_array_equal(bufs[gi][2][s].cpu().numpy(), rng_graphs[gi][2])
