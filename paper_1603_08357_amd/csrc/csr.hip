@@ -311,9 +311,10 @@ __global__ void __launch_bounds__(kTileBlock)
 //      kCrossChunk pairs has at most 2 kCrossChunk distinct labels, so the
 //      table of kCrossSlots never fills), and the pairs are joined there with
 //      the LDS union-find on slot numbers;
-//   3. every table entry that is not the root of its local component issues
-//      one global join, Algorithm 1 in global memory, with the label at the
-//      component's root slot.
+//   3. every table entry that is not the root of its local component is
+//      listed (compactly, so that every lane of the next step has work), and
+//      each listed entry issues one global join, Algorithm 1 in global
+//      memory, with the label at the component's root slot.
 // The global joins are a spanning forest of the chunk's pairs, so the result
 // is the same connectivity with far fewer global chases and atomics: above
 // the threshold, where nearly every leaving bond belongs to the spanning
@@ -372,6 +373,11 @@ __global__ void __launch_bounds__(kCrossBlock)
     k_csr_cross(const int2* __restrict__ pairs, const int2* __restrict__ seg, int32_t* label) {
   __shared__ int32_t keys[kCrossSlots];
   __shared__ uint16_t lpar[kCrossSlots];
+  // the join list: at most one per table entry less one per component, so
+  // kCrossSlots - 1 entries; its last word is the list's length (this keeps
+  // the kernel at 40 KB of LDS, four workgroups per CU)
+  __shared__ uint32_t joins[kCrossSlots];
+  uint32_t& n_join = joins[kCrossSlots - 1];
   constexpr int P = kCrossPer;
   const int tid = threadIdx.x;
   const uint32_t tile = xcd_block_id();
@@ -381,6 +387,7 @@ __global__ void __launch_bounds__(kCrossBlock)
   bool unused = false;
   for (int32_t c0 = 0; c0 < count; c0 += kCrossChunk) {
     for (int s = tid; s < kCrossSlots; s += kCrossBlock) keys[s] = kEmpty;
+    if (tid == 0) n_join = 0;
     for (int w = tid; w < kCrossSlots / 2; w += kCrossBlock)
       reinterpret_cast<uint32_t*>(lpar)[w] = (uint32_t)(2 * w) | ((uint32_t)(2 * w + 1) << 16);
     __syncthreads();
@@ -411,22 +418,30 @@ __global__ void __launch_bounds__(kCrossBlock)
     }
     lds16_unite_lockstep<P, 1>(lpar, a, b);
     __syncthreads();
-    // 3. one global join per entry below its local root, kCrossJoinPer per
-    //    lane in lockstep
+    // 3. the entries below their local root, listed compactly (slot and
+    //    root slot, 16 bits each; one LDS atomic per wavefront and round)
+    for (int s0 = 0; s0 < kCrossSlots; s0 += kCrossBlock) {
+      const int s = s0 + tid;
+      const int32_t r = keys[s] != kEmpty ? lds16_find(lpar, s) : s;
+      const uint32_t slot = reserve_slots(r != s ? 1u : 0u, &n_join);
+      if (r != s) joins[slot] = ((uint32_t)s << 16) | (uint32_t)r;
+    }
+    __syncthreads();
+    // 4. one global join per listed entry, kCrossJoinPer per lane in lockstep
     constexpr int J = kCrossJoinPer;
-    for (int s0 = 0; s0 < kCrossSlots; s0 += J * kCrossBlock) {
+    const int32_t nj = (int32_t)n_join;
+    for (int32_t j0 = 0; j0 < nj; j0 += J * kCrossBlock) {
       int32_t x[J], y[J];
 #pragma unroll
       for (int k = 0; k < J; ++k) {
-        const int s = s0 + k * kCrossBlock + tid;
-        const int32_t key = keys[s];
-        const int32_t r = key != kEmpty ? lds16_find(lpar, s) : s;
-        x[k] = r != s ? key : 0;
-        y[k] = r != s ? keys[r] : 0;
+        const int32_t j = j0 + k * kCrossBlock + tid;
+        const uint32_t e = joins[j < nj ? j : 0];
+        x[k] = j < nj ? keys[e >> 16] : 0;
+        y[k] = j < nj ? keys[e & 0xFFFFu] : 0;
       }
       unite_lockstep<J, 2, false>(label, x, y, unused);
     }
-    __syncthreads();  // the table is reset for the next chunk
+    __syncthreads();  // the table and the list are reset for the next chunk
   }
 }
 
