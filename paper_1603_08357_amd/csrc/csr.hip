@@ -27,7 +27,7 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
-constexpr int kLdsRounds = 2;  // unconditional chase rounds before the voted ones
+constexpr int kLdsRounds = 2;  // lockstep pointer-following rounds in LDS before the fallbacks
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
 // Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
@@ -72,6 +72,40 @@ __device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, i
   return true;
 }
 
+// Join a group of four bonds per lane in LDS, compacted across the
+// wavefront: the occupied in-tile bonds (bit j of `act`; `packed` holds the
+// tile-relative ends, 16 bits each) are gathered in the wavefront's staging
+// area -- positions from a prefix count done with three ballots, since each
+// lane has at most four -- and joined two per lane in lockstep, so the
+// unoccupied majority of bond slots costs no join work.  The staging area
+// is private to the wavefront, whose LDS accesses complete in order.
+__device__ __forceinline__ void tile_join_compact(uint16_t* par, uint32_t* stage, uint32_t act,
+                                                  const uint32_t (&packed)[4]) {
+  const uint32_t mine = __popc(act);
+  const uint64_t b0 = __ballot(mine & 1u), b1 = __ballot(mine & 2u), b2 = __ballot(mine & 4u);
+  auto below = [](uint64_t m) {  // set bits of m in lanes below this one
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  };
+  uint32_t pos = below(b0) + 2u * below(b1) + 4u * below(b2);
+  const uint32_t total =
+      (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if ((act >> j) & 1u) stage[pos++] = packed[j];
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t base = 0; base < total; base += 128) {
+    int32_t a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t i = base + 64u * h + lane;
+      const uint32_t v = i < total ? stage[i] : 0u;  // (0, 0): a no-op bond
+      a[h] = (int32_t)(v >> 16);
+      b[h] = (int32_t)(v & 0xFFFFu);
+    }
+    lds16_unite_lockstep<2, kLdsRounds>(par, a, b);
+  }
+}
+
 // Reserve `mine` consecutive slots of the tile's pair segment for this lane:
 // one LDS atomic per wavefront (inclusive scan of the lanes' counts with
 // cross-lane shuffles).  Returns the lane's first slot.
@@ -111,7 +145,9 @@ __global__ void __launch_bounds__(kTileBlock)
                const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
                int2* __restrict__ pairs, int2* __restrict__ seg) {
   __shared__ uint16_t par[kCsrTile];  // tile-relative parents, 16 bits each
+  __shared__ uint32_t stage[kTileBlock / 64][256];  // per-wavefront join staging
   __shared__ uint32_t n_out;
+  const int wave = threadIdx.x >> 6;
   const int64_t lo = (int64_t)blockIdx.x << kTileShift;
   const int32_t cnt = (int32_t)min((int64_t)kCsrTile, n - lo);
   const int tid = threadIdx.x;
@@ -171,22 +207,23 @@ __global__ void __launch_bounds__(kTileBlock)
       load(k + 1, 0, cn[0], on[0]);
       load(k + 1, 1, cn[1], on[1]);
       uint32_t leave = 0;  // bit 4u+j: bond j of group u leaves the tile
-      int32_t ja[8], jb[8];  // the lane's bonds inside the tile; (0, 0) for none
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
         const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+        uint32_t act = 0;  // bit j: bond j of the group is occupied and inside the tile
+        uint32_t packed[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool on = ((o[u] >> (8 * j)) & 0xFFu) != 0;
           const uint32_t vl = (uint32_t)c4[j] - (uint32_t)lo;  // lo + cnt <= 2^31
           const bool inside = vl < (uint32_t)cnt;
           if (on && !inside) leave |= 1u << (4 * u + j);
-          ja[4 * u + j] = on && inside ? affine_row(e + j, magic) : 0;
-          jb[4 * u + j] = on && inside ? (int32_t)vl : 0;
+          act |= (uint32_t)(on && inside) << j;
+          packed[j] = ((uint32_t)affine_row(e + j, magic) << 16) | (vl & 0xFFFFu);
         }
+        tile_join_compact(par, stage[wave], act, packed);
       }
-      lds16_unite_lockstep<8, kLdsRounds>(par, ja, jb);
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
