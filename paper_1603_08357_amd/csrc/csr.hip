@@ -72,37 +72,49 @@ __device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, i
   return true;
 }
 
-// Join a group of four bonds per lane in LDS, compacted across the
-// wavefront: the occupied in-tile bonds (bit j of `act`; `packed` holds the
-// tile-relative ends, 16 bits each) are gathered in the wavefront's staging
-// area -- positions from a prefix count done with three ballots, since each
-// lane has at most four -- and joined two per lane in lockstep, so the
-// unoccupied majority of bond slots costs no join work.  The staging area
-// is private to the wavefront, whose LDS accesses complete in order.
-__device__ __forceinline__ void tile_join_compact(uint16_t* par, uint32_t* stage, uint32_t act,
-                                                  const uint32_t (&packed)[4]) {
+// Joins of the affine tile path, compacted across the wavefront: each group
+// of four bonds per lane appends its occupied in-tile bonds (bit j of `act`;
+// `packed` holds the tile-relative ends, 16 bits each) to the wavefront's
+// staging stack -- positions from a prefix count done with three ballots,
+// since each lane has at most four -- and whenever the stack holds a full
+// batch, the top kJoinPer * 64 entries are joined kJoinPer per lane in
+// lockstep.  So the unoccupied majority of bond slots costs no join work and
+// every lockstep join is full; `staged` (wavefront-uniform) carries the rest
+// to the next group.  The stack is private to the wavefront, whose LDS
+// accesses complete in order.
+constexpr int kJoinPer = 2;
+constexpr int kJoinBatch = 64 * kJoinPer;
+constexpr int kStageCap = kJoinBatch - 1 + 256;  // leftover + one group of 64 x 4
+
+__device__ __forceinline__ void join_batch(uint16_t* par, const uint32_t* stage, uint32_t base,
+                                           uint32_t limit) {
+  const uint32_t lane = threadIdx.x & 63u;
+  int32_t a[kJoinPer], b[kJoinPer];
+#pragma unroll
+  for (int h = 0; h < kJoinPer; ++h) {
+    const uint32_t i = base + 64u * h + lane;
+    const uint32_t v = i < limit ? stage[i] : 0u;  // (0, 0): a no-op bond
+    a[h] = (int32_t)(v >> 16);
+    b[h] = (int32_t)(v & 0xFFFFu);
+  }
+  lds16_unite_lockstep<kJoinPer, kLdsRounds>(par, a, b);
+}
+
+__device__ __forceinline__ void tile_join_compact(uint16_t* par, uint32_t* stage, uint32_t& staged,
+                                                  uint32_t act, const uint32_t (&packed)[4]) {
   const uint32_t mine = __popc(act);
   const uint64_t b0 = __ballot(mine & 1u), b1 = __ballot(mine & 2u), b2 = __ballot(mine & 4u);
   auto below = [](uint64_t m) {  // set bits of m in lanes below this one
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   };
-  uint32_t pos = below(b0) + 2u * below(b1) + 4u * below(b2);
-  const uint32_t total =
-      (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+  uint32_t pos = staged + below(b0) + 2u * below(b1) + 4u * below(b2);
+  staged += (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if ((act >> j) & 1u) stage[pos++] = packed[j];
-  const uint32_t lane = threadIdx.x & 63u;
-  for (uint32_t base = 0; base < total; base += 128) {
-    int32_t a[2], b[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t i = base + 64u * h + lane;
-      const uint32_t v = i < total ? stage[i] : 0u;  // (0, 0): a no-op bond
-      a[h] = (int32_t)(v >> 16);
-      b[h] = (int32_t)(v & 0xFFFFu);
-    }
-    lds16_unite_lockstep<2, kLdsRounds>(par, a, b);
+  while (staged >= (uint32_t)kJoinBatch) {
+    staged -= kJoinBatch;
+    join_batch(par, stage, staged, staged + kJoinBatch);
   }
 }
 
@@ -145,7 +157,7 @@ __global__ void __launch_bounds__(kTileBlock)
                const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
                int2* __restrict__ pairs, int2* __restrict__ seg) {
   __shared__ uint16_t par[kCsrTile];  // tile-relative parents, 16 bits each
-  __shared__ uint32_t stage[kTileBlock / 64][256];  // per-wavefront join staging
+  __shared__ uint32_t stage[kTileBlock / 64][kStageCap];  // per-wavefront join staging
   __shared__ uint32_t n_out;
   const int wave = threadIdx.x >> 6;
   const int64_t lo = (int64_t)blockIdx.x << kTileShift;
@@ -203,6 +215,7 @@ __global__ void __launch_bounds__(kTileBlock)
     };
     load(0, 0, c[0], o[0]);
     load(0, 1, c[1], o[1]);
+    uint32_t staged = 0;  // entries on this wavefront's staging stack
     for (int32_t k = 0; k < iters; ++k) {
       load(k + 1, 0, cn[0], on[0]);
       load(k + 1, 1, cn[1], on[1]);
@@ -222,7 +235,7 @@ __global__ void __launch_bounds__(kTileBlock)
           act |= (uint32_t)(on && inside) << j;
           packed[j] = ((uint32_t)affine_row(e + j, magic) << 16) | (vl & 0xFFFFu);
         }
-        tile_join_compact(par, stage[wave], act, packed);
+        tile_join_compact(par, stage[wave], staged, act, packed);
       }
       uint32_t slot = reserve_slots(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
@@ -242,6 +255,7 @@ __global__ void __launch_bounds__(kTileBlock)
         o[u] = on[u];
       }
     }
+    if (staged > 0) join_batch(par, stage[wave], 0, staged);  // what is left on the stack
     // the last group, when it straddles the end of the tile
     if (tid == 0 && full * 4 < nb) {
       for (int32_t x = 4 * full; x < nb; ++x) {
