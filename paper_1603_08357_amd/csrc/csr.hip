@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(kTileBlock)
 // cluster, a chunk reduces to a handful of joins instead of thousands of
 // atomics on the same few addresses.
 constexpr int kCrossBlock = 256;
-constexpr int kCrossPer = 8;  // pairs (and later joins) a lane carries in lockstep
+constexpr int kCrossPer = 4;  // pairs (and later joins) a lane carries in lockstep
 constexpr int kCrossJoinPer = 4;  // global joins a lane carries in lockstep
 constexpr int kCrossChunk = kCrossPer * kCrossBlock;
 constexpr int kCrossSlots = 2 * kCrossChunk;
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(kCrossBlock)
 // the window (every thread sharing that parent then finds the root in LDS).
 // Every value written is the site's final root; the window goes back with
 // 16-byte stores.  Windows are renumbered so each XCD takes a contiguous run.
-constexpr int kFlatWin = 32768;
+constexpr int kFlatWin = 16384;
 constexpr int kFlatBlock = 1024;
 constexpr int kFlatPer = 8;  // sites a lane resolves in lockstep
 
