@@ -347,7 +347,40 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   __syncthreads();
-  for (int t = tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds16_find(par, t));
+  // the tile's labels: each site's tile-local root (its cluster's minimum in
+  // the tile), eight sites per lane resolved together and stored 16 bytes at
+  // a time when the label array allows it
+  const int32_t n4 = ((reinterpret_cast<uintptr_t>(label + lo) & 15) == 0) ? (cnt >> 2) : 0;
+  for (int32_t q0 = 0; q0 < n4; q0 += 2 * kTileBlock) {
+    int32_t x[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t q = q0 + h * kTileBlock + tid;
+      const uint2 w = reinterpret_cast<const uint2*>(par)[q < n4 ? q : 0];  // parents of 4q..4q+3
+      x[4 * h + 0] = (int32_t)(w.x & 0xFFFFu);
+      x[4 * h + 1] = (int32_t)(w.x >> 16);
+      x[4 * h + 2] = (int32_t)(w.y & 0xFFFFu);
+      x[4 * h + 3] = (int32_t)(w.y >> 16);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t p = lds16_ld(par + x[k]);
+      if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t q = q0 + h * kTileBlock + tid;
+      const int32_t b = (int32_t)lo;
+      if (q < n4)
+        reinterpret_cast<int4*>(label + lo)[q] =
+            make_int4(b + x[4 * h], b + x[4 * h + 1], b + x[4 * h + 2], b + x[4 * h + 3]);
+    }
+  }
+  for (int t = 4 * n4 + tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds16_find(par, t));
   if (tid == 0 && seg != nullptr) seg[blockIdx.x] = make_int2(e_begin - e0, (int32_t)n_out);
 }
 
@@ -372,7 +405,7 @@ __global__ void __launch_bounds__(kTileBlock)
 // cluster, a chunk reduces to a handful of joins instead of thousands of
 // atomics on the same few addresses.
 constexpr int kCrossBlock = 256;
-constexpr int kCrossPer = 4;  // pairs (and later joins) a lane carries in lockstep
+constexpr int kCrossPer = 2;  // pairs (and later joins) a lane carries in lockstep
 constexpr int kCrossJoinPer = 4;  // global joins a lane carries in lockstep
 constexpr int kCrossChunk = kCrossPer * kCrossBlock;
 constexpr int kCrossSlots = 2 * kCrossChunk;
