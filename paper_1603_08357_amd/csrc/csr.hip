@@ -27,6 +27,7 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
+constexpr int kLeaveBits = 5;  // a lane leaves at most 16 bonds per step: 5-bit counts
 constexpr int kLdsRounds = 2;  // lockstep pointer-following rounds in LDS before the fallbacks
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
@@ -118,23 +119,26 @@ __device__ __forceinline__ void tile_join_compact(uint16_t* par, uint32_t* stage
   }
 }
 
-// Reserve `mine` consecutive slots of the tile's pair segment for this lane:
-// one LDS atomic per wavefront (inclusive scan of the lanes' counts with
-// cross-lane shuffles).  Returns the lane's first slot.
+// Reserve `mine` (< 2^BITS) consecutive slots of a list for this lane: the
+// lane's offset is a prefix count over the wavefront done with BITS ballots,
+// and one LDS atomic per wavefront takes the wavefront's total.  Returns the
+// lane's first slot.
+template <int BITS>
 __device__ __forceinline__ uint32_t reserve_slots(uint32_t mine, uint32_t* n_out) {
-  const int lane = threadIdx.x & 63;
-  uint32_t incl = mine;
+  uint32_t below = 0, total = 0;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t up = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += up;
+  for (int i = 0; i < BITS; ++i) {
+    const uint64_t m = __ballot((mine >> i) & 1u);
+    below += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << i;
+    total += (uint32_t)__popcll(m) << i;
   }
-  const uint32_t total = __shfl(incl, 63, 64);
   uint32_t base = 0;
-  if (lane == 63 && total)
-    base = __hip_atomic_fetch_add(n_out, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  base = __shfl(base, 63, 64);
-  return base + incl - mine;
+  if (total != 0) {  // wavefront-uniform
+    if ((threadIdx.x & 63u) == 0)
+      base = __hip_atomic_fetch_add(n_out, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+  }
+  return base + below;
 }
 
 // One workgroup per tile, in two phases.
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(kTileBlock)
         }
         tile_join_compact(par, stage[wave], staged, act, packed);
       }
-      uint32_t slot = reserve_slots(__popc(leave), &n_out);
+      uint32_t slot = reserve_slots<kLeaveBits>(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -314,7 +318,7 @@ __global__ void __launch_bounds__(kTileBlock)
         }
         lds16_unite_lockstep<kDegFast, kLdsRounds>(par, ja, jb);
       }
-      uint32_t slot = reserve_slots(__popc(leave), &n_out);
+      uint32_t slot = reserve_slots<kLeaveBits>(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
         for (int k = 0; k < kRowsPerThread; ++k)
@@ -507,7 +511,7 @@ __global__ void __launch_bounds__(kCrossBlock)
     for (int s0 = 0; s0 < kCrossSlots; s0 += kCrossBlock) {
       const int s = s0 + tid;
       const int32_t r = keys[s] != kEmpty ? lds16_find(lpar, s) : s;
-      const uint32_t slot = reserve_slots(r != s ? 1u : 0u, &n_join);
+      const uint32_t slot = reserve_slots<1>(r != s ? 1u : 0u, &n_join);
       if (r != s) joins[slot] = ((uint32_t)s << 16) | (uint32_t)r;
     }
     __syncthreads();
@@ -597,10 +601,12 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, i
     for (int k = 0; k < K; ++k) {
       if (!need[k]) continue;
       const int32_t t = t0 + k * kFlatBlock + tid;
-      if (pin[k] < (uint32_t)cnt)
-        lds_st(w + pin[k], x[k]);  // the parent's final root, for the sites sharing it
-      else if (x[k] != q[k])
-        lab_st(label + p[k], x[k]);
+      if (x[k] != q[k]) {  // the parent's final root, for the sites sharing it
+        if (pin[k] < (uint32_t)cnt)
+          lds_st(w + pin[k], x[k]);
+        else
+          lab_st(label + p[k], x[k]);
+      }
       lds_st(w + t, x[k]);
     }
   }
