@@ -408,9 +408,9 @@ __global__ void __launch_bounds__(kTileBlock)
 // the threshold, where nearly every leaving bond belongs to the spanning
 // cluster, a chunk reduces to a handful of joins instead of thousands of
 // atomics on the same few addresses.
-constexpr int kCrossBlock = 256;
-constexpr int kCrossPer = 2;  // pairs (and later joins) a lane carries in lockstep
-constexpr int kCrossJoinPer = 4;  // global joins a lane carries in lockstep
+constexpr int kCrossBlock = 512;
+constexpr int kCrossPer = 1;  // pairs (and later joins) a lane carries in lockstep
+constexpr int kCrossJoinPer = 2;  // global joins a lane carries in lockstep
 constexpr int kCrossChunk = kCrossPer * kCrossBlock;
 constexpr int kCrossSlots = 2 * kCrossChunk;
 constexpr int32_t kEmpty = -1;
