@@ -183,42 +183,59 @@ __global__ void __launch_bounds__(kTileBlock)
   const __amdgpu_buffer_rsrc_t ro =
       make_rsrc(HAS_OCC ? occ + e_begin : nullptr, fast && HAS_OCC ? (uint32_t)e_count : 0u);
 
-  for (int w = tid; w < kCsrTile / 2; w += kTileBlock)  // par[t] = t, two entries per word
-    reinterpret_cast<uint32_t*>(par)[w] = (uint32_t)(2 * w) | ((uint32_t)(2 * w + 1) << 16);
+  // the affine stream's first bond loads go out before the check below, so
+  // their latency overlaps it (unused if the tile turns out not affine)
+  const int32_t nb = deg * cnt;
+  const int32_t full = nb >> 2;  // groups of four bonds entirely inside the tile
+  const int32_t iters = (((nb + 3) >> 2) + 2 * kTileBlock - 1) / (2 * kTileBlock);
+  int4 c[2], cn[2];
+  uint32_t o[2], on[2];
+  auto load = [&](int32_t k, int u, int4& cv, uint32_t& ov) {
+    const int32_t q = (2 * k + u) * kTileBlock + tid;
+    const uint32_t off = q < full ? 4u * (uint32_t)q : kOffNone;
+    cv = buf_i32x4(rc, off * 4u);
+    ov = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
+  };
+  if (affine_try) {
+    load(0, 0, c[0], o[0]);
+    load(0, 1, c[1], o[1]);
+  }
+
+  for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {  // par[t] = t, 16 bytes at a time
+    const uint32_t t = 8u * (uint32_t)w;
+    reinterpret_cast<uint4*>(par)[w] =
+        make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16),
+                   (t + 6) | ((t + 7) << 16));
+  }
   if (tid == 0) n_out = 0;
 
-  // ---- A: affine check (rows 0..cnt of row_ptr; out-of-range reads are 0)
+  // ---- A: affine check of row_ptr[lo .. lo+cnt) (the entry at lo+cnt is
+  // e_begin + deg*cnt by the choice of deg), 16 bytes per load, eight loads
+  // in flight per lane; out-of-range reads are 0 and are not compared
   bool ok = affine_try;
   if (affine_try) {
-    constexpr int kBatch = 16;
-    for (int t0 = 0; t0 <= cnt; t0 += kBatch * kTileBlock) {
-      int32_t v[kBatch];
+    const int32_t g4 = cnt >> 2;  // groups of four rows
+    for (int32_t g0 = 0; g0 < g4; g0 += 8 * kTileBlock) {
+      int4 v[8];
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) v[k] = buf_i32(rp, 4u * (uint32_t)(t0 + k * kTileBlock + tid));
+      for (int k = 0; k < 8; ++k) {
+        const int32_t g = g0 + k * kTileBlock + tid;
+        v[k] = buf_i32x4(rp, g < g4 ? 16u * (uint32_t)g : kOffNone * 4u);
+      }
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        const int32_t t = t0 + k * kTileBlock + tid;
-        if (t <= cnt) ok = ok && v[k] - e_begin == deg * t;
+      for (int k = 0; k < 8; ++k) {
+        const int32_t g = g0 + k * kTileBlock + tid;
+        const int32_t b = e_begin + deg * 4 * g;
+        if (g < g4)
+          ok = ok && v[k].x == b && v[k].y == b + deg && v[k].z == b + 2 * deg && v[k].w == b + 3 * deg;
       }
     }
+    for (int32_t t = 4 * g4 + tid; t < cnt; t += kTileBlock) ok = ok && buf_i32(rp, 4u * (uint32_t)t) == e_begin + deg * t;
   }
   const bool affine = __syncthreads_and(ok) != 0;  // also publishes the LDS init
 
   if (affine) {
     // ---- B, affine: bond groups of four
-    const int32_t nb = deg * cnt;
-    const int32_t full = nb >> 2;  // groups entirely inside the tile
-    const int32_t iters = (((nb + 3) >> 2) + 2 * kTileBlock - 1) / (2 * kTileBlock);
-    int4 c[2], cn[2];
-    uint32_t o[2], on[2];
-    auto load = [&](int32_t k, int u, int4& cv, uint32_t& ov) {
-      const int32_t q = (2 * k + u) * kTileBlock + tid;
-      const uint32_t off = q < full ? 4u * (uint32_t)q : kOffNone;
-      cv = buf_i32x4(rc, off * 4u);
-      ov = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
-    };
-    load(0, 0, c[0], o[0]);
-    load(0, 1, c[1], o[1]);
     uint32_t staged = 0;  // entries on this wavefront's staging stack
     for (int32_t k = 0; k < iters; ++k) {
       load(k + 1, 0, cn[0], on[0]);
