@@ -234,15 +234,31 @@ __device__ __forceinline__ void lds_st(int32_t* p, int32_t v) {
 
 // A tile of up to 65536 sites keeps its parent array as 16-bit tile-relative
 // ids (128 KB of LDS).  Loads and path-halving stores are 16-bit LDS accesses;
-// LDS has no 16-bit atomic min, so the min is a compare-and-swap loop on the
+// LDS has no 16-bit atomic min: lds16_min is a compare-and-swap loop on the
 // 32-bit word holding the entry (the neighbouring entry's concurrent 16-bit
-// stores just make the swap retry).
+// stores just make the swap retry), and the lockstep union links with a
+// masked-or on the entry's half of the word instead.
 
 __device__ __forceinline__ int32_t lds16_ld(const uint16_t* p) {
   return (int32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds16_st(uint16_t* p, int32_t v) {
   __hip_atomic_store(p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+
+// One masked-or per lane on the 32-bit LDS word at byte offset off (LDS
+// offsets are the low 32 bits of a generic pointer to shared memory): the
+// bits of mask take the values of bits, atomically, and the old word comes
+// back.  lds_wait completes it (the compiler does not count inline LDS
+// operations, so the wait is explicit and ties the result to it).
+__device__ __forceinline__ uint32_t lds_mskor_issue(uint32_t off, uint32_t mask, uint32_t bits) {
+  uint32_t r;
+  asm volatile("ds_mskor_rtn_b32 %0, %1, %2, %3" : "=v"(r) : "v"(off), "v"(mask), "v"(bits) : "memory");
+  return r;
+}
+__device__ __forceinline__ void lds_wait(uint32_t& r) {
+  asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(r) : : "memory");
 }
 
 // atomicMin of entry x with v; returns the previous value of the entry
@@ -305,10 +321,19 @@ __device__ __forceinline__ void lds16_unite(uint16_t* par, int32_t a, int32_t b)
 // bond with a[k] == b[k] does nothing): the first parent loads of all 2P ends
 // are issued together, then ROUNDS pointer-following rounds in which every
 // end steps (a root steps onto itself), then the rare longer chases one by
-// one.  Algorithm 1's minimum is then taken for all P bonds together: one
-// word load and at most one compare-and-swap each, the few that lose a race
-// retrying through lds16_min, and the join loop continuing only where the
-// higher root was no longer a root.
+// one.  The link of Algorithm 1 is then made for all P bonds together, one
+// round per LDS round trip: the higher root's 16-bit half of its word is
+// overwritten with the lower root by a masked-or (one atomic, no word load,
+// no compare-and-swap to lose against the neighbouring entry), and the old
+// parent comes back.  Old == higher root: it was a root, done.  Old == lower
+// root: already linked, done.  Otherwise the higher root had been linked to
+// `old` meanwhile; that link has just been replaced, so the join loop goes on
+// with (old, lower root), as Algorithm 1 does after an atomicMin that did not
+// find a root.  Every overwritten link is thus rejoined by the lane that
+// overwrote it, a parent always stays below its child, and the larger end of
+// the pair strictly decreases each round, so the loop ends; the final
+// forest, hence each tile component's root (its smallest site), is the one
+// the atomicMin form gives.
 template <int P, int ROUNDS>
 __device__ __forceinline__ void lds16_unite_lockstep(uint16_t* par, int32_t (&a)[P], int32_t (&b)[P]) {
   int32_t pa[P], pb[P];
@@ -335,37 +360,34 @@ __device__ __forceinline__ void lds16_unite_lockstep(uint16_t* par, int32_t (&a)
     hi[k] = max(a[k], b[k]);
     lo[k] = min(a[k], b[k]);
   }
-  uint32_t* w32 = reinterpret_cast<uint32_t*>(par);
-  uint32_t w[P];
+  const uint32_t base = (uint32_t)reinterpret_cast<uintptr_t>(par);  // LDS offset
+  bool go[P];
 #pragma unroll
-  for (int k = 0; k < P; ++k)
-    w[k] = __hip_atomic_load(w32 + (hi[k] >> 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  int32_t old[P];
+  for (int k = 0; k < P; ++k) go[k] = hi[k] != lo[k];
+  for (;;) {
+    bool any = false;
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const uint32_t sh = (uint32_t)(hi[k] & 1) * 16u;
-    old[k] = (int32_t)((w[k] >> sh) & 0xFFFFu);
-    if (old[k] > lo[k]) {  // implies hi != lo
-      uint32_t seen = w[k];
-      const uint32_t next = (w[k] & ~(0xFFFFu << sh)) | ((uint32_t)lo[k] << sh);
-      if (!__hip_atomic_compare_exchange_strong(w32 + (hi[k] >> 1), &seen, next, __ATOMIC_RELAXED,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-        old[k] = lds16_min(par, hi[k], lo[k]);
+    for (int k = 0; k < P; ++k) any = any || go[k];
+    if (!__any(any)) break;
+    // a lane with nothing left issues an empty mask on its own word, so all
+    // P operations of every lane are in flight together
+    uint32_t ret[P], sh[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      sh[k] = (uint32_t)(hi[k] & 1) * 16u;
+      ret[k] = lds_mskor_issue(base + 4u * (uint32_t)(hi[k] >> 1), go[k] ? 0xFFFFu << sh[k] : 0u,
+                               go[k] ? (uint32_t)lo[k] << sh[k] : 0u);
     }
-  }
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    int32_t r1 = old[k], r2 = lo[k];
-    if (r1 == r2 || r1 == hi[k]) continue;
-    while (r1 != r2) {
-      if (r1 < r2) {
-        const int32_t t = r1;
-        r1 = r2;
-        r2 = t;
+    for (int k = 0; k < P; ++k) lds_wait(ret[k]);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int32_t old = (int32_t)((ret[k] >> sh[k]) & 0xFFFFu);
+      if (go[k] && (old == hi[k] || old == lo[k])) go[k] = false;
+      if (go[k]) {
+        hi[k] = max(old, lo[k]);
+        lo[k] = min(old, lo[k]);
       }
-      const int32_t o = lds16_min(par, r1, r2);
-      if (o == r2 || o == r1) break;
-      r1 = o;
     }
   }
 }
