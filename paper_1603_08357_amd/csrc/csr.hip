@@ -28,7 +28,7 @@ constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
 constexpr int kLeaveBits = 5;  // a lane leaves at most 16 bonds per step: 5-bit counts
-constexpr int kLdsRounds = 2;  // lockstep pointer-following rounds in LDS before the fallbacks
+constexpr int kLdsRounds = 4;  // lockstep pointer-following rounds in LDS before the fallbacks
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
 // Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
@@ -83,7 +83,7 @@ __device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, i
 // every lockstep join is full; `staged` (wavefront-uniform) carries the rest
 // to the next group.  The stack is private to the wavefront, whose LDS
 // accesses complete in order.
-constexpr int kJoinPer = 2;
+constexpr int kJoinPer = 1;  // one join per lane: with the masked-or link, more only add latency
 constexpr int kJoinBatch = 64 * kJoinPer;
 constexpr int kStageCap = kJoinBatch - 1 + 256;  // leftover + one group of 64 x 4
 
