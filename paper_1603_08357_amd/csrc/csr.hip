@@ -27,7 +27,10 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
+constexpr int kGroupsPerIter = 3;  // groups of four bonds per lane per step (affine path)
 constexpr int kLeaveBits = 5;  // a lane leaves at most 16 bonds per step: 5-bit counts
+static_assert(4 * kGroupsPerIter < (1 << kLeaveBits) && kRowsPerThread * kDegFast < (1 << kLeaveBits),
+              "a lane's leaving bonds per step must fit a count of kLeaveBits bits");
 constexpr int kLdsRounds = 4;  // lockstep pointer-following rounds in LDS before the fallbacks
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
 
@@ -141,15 +144,16 @@ __device__ __forceinline__ uint32_t reserve_slots(uint32_t mine, uint32_t* n_out
   return base + below;
 }
 
-// One workgroup per tile, in two phases.
-// A. Is the tile affine (row_ptr[lo + t] = e_begin + d*t, 1 <= d <= 4)?  Every
-//    lane checks a strided share of the tile's row_ptr; one vote.
-// B. Affine tiles stream their d*cnt bonds in groups of four: lane tid takes
-//    groups (2k+u)*kTileBlock + tid (u = 0, 1) at iteration k with one 16-byte
-//    col load and one 4-byte occ load per group, both fully coalesced, and
-//    requests iteration k+1's groups before joining iteration k's, so no
-//    barrier or wait on another wavefront is ever on the way.  Other CSR
-//    graphs take the row path: kRowsPerThread rows per lane, the first
+// One workgroup per tile.  A tile whose bond count is d*cnt (1 <= d <= 4) is
+// read as affine (row_ptr[lo + t] = e_begin + d*t): its bonds stream in
+// groups of four, lane tid taking groups (G*k+u)*kTileBlock + tid (u < G =
+// kGroupsPerIter) at step k with one 16-byte col load and one 4-byte occ load
+// per group, both fully coalesced, and requesting step k+1's groups before
+// joining step k's, so no barrier or wait on another wavefront is ever on
+// the way.  The affine form is verified during the same stream (16 bytes of
+// row_ptr per lane and step) and voted on at the end; a tile that fails
+// starts over on the row path, as do all other CSR graphs: kRowsPerThread
+// rows per lane, the first
 //    kDegFast bonds of each row in one batch of buffer loads (longer rows in a
 //    loop), the next rows' row_ptr requested ahead.
 // Buffer resources are based at the tile's first row and first bond, so
@@ -183,67 +187,62 @@ __global__ void __launch_bounds__(kTileBlock)
   const __amdgpu_buffer_rsrc_t ro =
       make_rsrc(HAS_OCC ? occ + e_begin : nullptr, fast && HAS_OCC ? (uint32_t)e_count : 0u);
 
-  // the affine stream's first bond loads go out before the check below, so
-  // their latency overlaps it (unused if the tile turns out not affine)
+  // the affine stream's first bond loads go out before the LDS is set up
   const int32_t nb = deg * cnt;
   const int32_t full = nb >> 2;  // groups of four bonds entirely inside the tile
-  const int32_t iters = (((nb + 3) >> 2) + 2 * kTileBlock - 1) / (2 * kTileBlock);
-  int4 c[2], cn[2];
-  uint32_t o[2], on[2];
+  constexpr int G = kGroupsPerIter;
+  const int32_t iters = (((nb + 3) >> 2) + G * kTileBlock - 1) / (G * kTileBlock);
+  int4 c[G], cn[G];
+  uint32_t o[G], on[G];
   auto load = [&](int32_t k, int u, int4& cv, uint32_t& ov) {
-    const int32_t q = (2 * k + u) * kTileBlock + tid;
+    const int32_t q = (G * k + u) * kTileBlock + tid;
     const uint32_t off = q < full ? 4u * (uint32_t)q : kOffNone;
     cv = buf_i32x4(rc, off * 4u);
     ov = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
   };
   if (affine_try) {
-    load(0, 0, c[0], o[0]);
-    load(0, 1, c[1], o[1]);
+#pragma unroll
+    for (int u = 0; u < G; ++u) load(0, u, c[u], o[u]);
   }
 
-  for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {  // par[t] = t, 16 bytes at a time
-    const uint32_t t = 8u * (uint32_t)w;
-    reinterpret_cast<uint4*>(par)[w] =
-        make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16),
-                   (t + 6) | ((t + 7) << 16));
-  }
-  if (tid == 0) n_out = 0;
+  auto init_par = [&]() {
+    for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {  // par[t] = t, 16 bytes at a time
+      const uint32_t t = 8u * (uint32_t)w;
+      reinterpret_cast<uint4*>(par)[w] =
+          make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16),
+                     (t + 6) | ((t + 7) << 16));
+    }
+    if (tid == 0) n_out = 0;
+  };
+  init_par();
+  __syncthreads();
 
-  // ---- A: affine check of row_ptr[lo .. lo+cnt) (the entry at lo+cnt is
-  // e_begin + deg*cnt by the choice of deg), 16 bytes per load, eight loads
-  // in flight per lane; out-of-range reads are 0 and are not compared
-  bool ok = affine_try;
+  // ---- B, affine, speculatively: bond groups of four, read as if row_ptr
+  // were e_begin + deg*r.  The rows are checked against that on the way (16
+  // bytes of row_ptr per lane and step, in flight with the bond loads); a
+  // tile that fails the check starts again on the row path, which rewrites
+  // the tile's leaving pairs from the start of its segment.  Every index the
+  // affine reading forms stays inside the tile and its resources either way.
+  bool affine = false;
   if (affine_try) {
     const int32_t g4 = cnt >> 2;  // groups of four rows
-    for (int32_t g0 = 0; g0 < g4; g0 += 8 * kTileBlock) {
-      int4 v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int32_t g = g0 + k * kTileBlock + tid;
-        v[k] = buf_i32x4(rp, g < g4 ? 16u * (uint32_t)g : kOffNone * 4u);
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int32_t g = g0 + k * kTileBlock + tid;
-        const int32_t b = e_begin + deg * 4 * g;
-        if (g < g4)
-          ok = ok && v[k].x == b && v[k].y == b + deg && v[k].z == b + 2 * deg && v[k].w == b + 3 * deg;
-      }
-    }
-    for (int32_t t = 4 * g4 + tid; t < cnt; t += kTileBlock) ok = ok && buf_i32(rp, 4u * (uint32_t)t) == e_begin + deg * t;
-  }
-  const bool affine = __syncthreads_and(ok) != 0;  // also publishes the LDS init
-
-  if (affine) {
-    // ---- B, affine: bond groups of four
+    auto rp_load = [&](int32_t g) { return buf_i32x4(rp, g < g4 ? 16u * (uint32_t)g : kOffNone * 4u); };
+    auto rp_ok = [&](int32_t g, const int4& v) {
+      const int32_t r0 = e_begin + deg * 4 * g;
+      return g >= g4 || (v.x == r0 && v.y == r0 + deg && v.z == r0 + 2 * deg && v.w == r0 + 3 * deg);
+    };
+    bool ok = true;
+    int4 rv = rp_load(tid), rvn;
     uint32_t staged = 0;  // entries on this wavefront's staging stack
     for (int32_t k = 0; k < iters; ++k) {
-      load(k + 1, 0, cn[0], on[0]);
-      load(k + 1, 1, cn[1], on[1]);
+#pragma unroll
+      for (int u = 0; u < G; ++u) load(k + 1, u, cn[u], on[u]);
+      rvn = rp_load((k + 1) * kTileBlock + tid);
+      ok = rp_ok(k * kTileBlock + tid, rv) && ok;
       uint32_t leave = 0;  // bit 4u+j: bond j of group u leaves the tile
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
+      for (int u = 0; u < G; ++u) {
+        const int32_t e = 4 * ((G * k + u) * kTileBlock + tid);
         const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
         uint32_t act = 0;  // bit j: bond j of the group is occupied and inside the tile
         uint32_t packed[4];
@@ -261,8 +260,8 @@ __global__ void __launch_bounds__(kTileBlock)
       uint32_t slot = reserve_slots<kLeaveBits>(__popc(leave), &n_out);
       if (leave) {  // static indices only: the register arrays must not spill
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int32_t e = 4 * ((2 * k + u) * kTileBlock + tid);
+        for (int u = 0; u < G; ++u) {
+          const int32_t e = 4 * ((G * k + u) * kTileBlock + tid);
           const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
 #pragma unroll
           for (int j = 0; j < 4; ++j)
@@ -271,12 +270,25 @@ __global__ void __launch_bounds__(kTileBlock)
         }
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < G; ++u) {
         c[u] = cn[u];
         o[u] = on[u];
       }
+      rv = rvn;
     }
+    // row groups past the loop's steps, then the last cnt mod 4 rows (the
+    // entry at lo+cnt is e_begin + deg*cnt by the choice of deg)
+    for (int32_t g = iters * kTileBlock + tid; g < g4; g += kTileBlock) ok = rp_ok(g, rp_load(g)) && ok;
+    for (int32_t t = 4 * g4 + tid; t < cnt; t += kTileBlock)
+      ok = buf_i32(rp, 4u * (uint32_t)t) == e_begin + deg * t && ok;
     if (staged > 0) join_batch(par, stage[wave], 0, staged);  // what is left on the stack
+    affine = __syncthreads_and(ok) != 0;
+    if (!affine) {
+      init_par();
+      __syncthreads();
+    }
+  }
+  if (affine) {
     // the last group, when it straddles the end of the tile
     if (tid == 0 && full * 4 < nb) {
       for (int32_t x = 4 * full; x < nb; ++x) {
@@ -384,7 +396,7 @@ __global__ void __launch_bounds__(kTileBlock)
       x[4 * h + 3] = (int32_t)(w.y >> 16);
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
 #pragma unroll
@@ -427,7 +439,8 @@ __global__ void __launch_bounds__(kTileBlock)
 // atomics on the same few addresses.
 constexpr int kCrossBlock = 512;
 constexpr int kCrossPer = 1;  // pairs (and later joins) a lane carries in lockstep
-constexpr int kCrossJoinPer = 2;  // global joins a lane carries in lockstep
+constexpr int kCrossJoinPer = 1;  // global joins a lane carries in lockstep
+constexpr int kCrossSplit = 1;  // workgroups per tile, each taking every kCrossSplit-th chunk
 constexpr int kCrossChunk = kCrossPer * kCrossBlock;
 constexpr int kCrossSlots = 2 * kCrossChunk;
 constexpr int32_t kEmpty = -1;
@@ -485,12 +498,13 @@ __global__ void __launch_bounds__(kCrossBlock)
   uint32_t& n_join = joins[kCrossSlots - 1];
   constexpr int P = kCrossPer;
   const int tid = threadIdx.x;
-  const uint32_t tile = xcd_block_id();
+  const uint32_t id = xcd_block_id();
+  const uint32_t tile = id / kCrossSplit;
   const int2 sc = seg[tile];
   const int2* p = pairs + sc.x;
   const int32_t count = sc.y;
   bool unused = false;
-  for (int32_t c0 = 0; c0 < count; c0 += kCrossChunk) {
+  for (int32_t c0 = (int32_t)(id % kCrossSplit) * kCrossChunk; c0 < count; c0 += kCrossSplit * kCrossChunk) {
     for (int s = tid; s < kCrossSlots; s += kCrossBlock) keys[s] = kEmpty;
     if (tid == 0) n_join = 0;
     for (int w = tid; w < kCrossSlots / 2; w += kCrossBlock)
@@ -659,7 +673,8 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<false>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
                col, occ, label, pairs, seg);
   if (n_tiles == 1) return CCL_OK;
-  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)n_tiles, kCrossBlock, 0, s, pairs, seg, label);
+  CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)(n_tiles * kCrossSplit), kCrossBlock, 0, s, pairs, seg,
+             label);
   if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
   const unsigned n_win = (unsigned)((n + kFlatWin - 1) / kFlatWin);
   CCL_LAUNCH("ccl_flatten_window", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);

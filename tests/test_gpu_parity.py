@@ -150,6 +150,29 @@ def test_csr_forms(ccl):
                                   oracle.label_csr(small.n_sites, small.row_ptr, small.col, small.occ))
 
 
+def test_csr_almost_affine(ccl):
+    """Tiles whose bond count is 3 per row although row_ptr is not affine: the
+    affine reading is verified while it streams and such a tile starts over
+    on the row path.  Tile 0 and the partial last tile are affine, tile 1
+    alternates degrees 2 and 4, tile 2 differs in one pair of rows only."""
+    T = 65536
+    n = 3 * T + 1000
+    deg = np.full(n, 3, dtype=np.int64)
+    deg[T:2 * T:2], deg[T + 1:2 * T:2] = 2, 4
+    deg[2 * T + 10], deg[2 * T + 11] = 2, 4
+    rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    rng = np.random.default_rng(23)
+    m = int(rp[-1])
+    site = np.repeat(np.arange(n), deg)
+    c = (site + rng.integers(-300, 301, m)) % n
+    far = rng.random(m) < 0.05
+    c[far] = rng.integers(0, n, int(far.sum()))
+    c = c.astype(np.int32)
+    o = (rng.random(m) < 0.45).astype(np.uint8)
+    np.testing.assert_array_equal(gpu_csr(ccl, rp, c, o), oracle.label_csr(n, rp, c, o))
+    np.testing.assert_array_equal(gpu_csr(ccl, rp, c, None), oracle.label_csr(n, rp, c, None))
+
+
 @pytest.mark.parametrize("p", [0.45, 0.5, 0.55])
 def test_config3_random_3_regular(ccl, p):
     """Bethe substitute: random 3-regular N = 2^24, random position."""
