@@ -97,6 +97,7 @@ def load_traffic(kernel: str, workload: str):
 
 COPY_PROBE_BYTES = 1 << 30  # the copy probe reads and writes this much
 KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
+                "k_ell_init": "ccl_ell_init", "k_ell_reduce": "ccl_ell_reduce",
                 "k_flatten": "ccl_flatten", "k_flatten_window": "ccl_flatten_window",
                 "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
 
@@ -272,6 +273,53 @@ def bench_edges(g, steps, warmup, cold=False):
         res["cold_step_ms"] = step_distribution(fn, steps, stream, before=make_flush())
         torch.cuda.empty_cache()
     return out, res
+
+
+def bench_ell(nn, occ, steps, warmup):
+    """ccl_label_ell on a (z_max, n) neighbour list already on the host."""
+    import torch
+    import paper_1603_08357_amd as ccl
+    dnn = torch.from_numpy(nn).cuda()
+    docc = torch.from_numpy(occ).cuda()
+    out = torch.empty(nn.shape[1], dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    fn = lambda: ccl.label_ell(dnn, docc, out=out, stream=stream)
+    ms, _ = time_steps(fn, steps, warmup, stream)
+    kern = traced_kernels(fn, steps)
+    res = {"ms_per_labeling": round(ms, 5), "Gsites_s": round(nn.shape[1] / (ms * 1e-3) / 1e9, 3),
+           "kernels": {k: round(v["mean_ms"], 5) for k, v in kern.items()}}
+    return out, res
+
+
+def bench_ell_set(steps, warmup, shells=22):
+    """The paper's own schedule on its neighbour-list form: the Cayley-tree
+    experiment (z = 3, p_c = 1/2) in standard and random numbering at 0.5 and
+    1.5 p_c, and the random 3-regular graph of 2^24 sites at p = 0.5."""
+    import numpy as np
+    import torch
+    import gen
+    import oracle
+    res = {}
+    for rp in (False, True):
+        for p in (0.25, 0.75):
+            t = gen.cayley_realization(shells, p, 7, rp)
+            nn, oe = gen.ell_from_edges(t.n_sites, t.src, t.dst, t.occ, 3)
+            out, r = bench_ell(nn, oe, steps, warmup)
+            key = f"cayley_G{shells}_{'random' if rp else 'standard'}_p{p}"
+            if rp and p == 0.75:
+                r["labels_match_oracle"] = bool(np.array_equal(
+                    out.cpu().numpy(), oracle.label_edges(t.n_sites, t.src, t.dst, t.occ)))
+            res[key] = r
+            del t, nn, oe, out
+            torch.cuda.empty_cache()
+    res["cayley_n_sites"] = gen.cayley_size(shells)
+    a = res[f"cayley_G{shells}_random_p0.75"]["ms_per_labeling"]
+    b = res[f"cayley_G{shells}_standard_p0.75"]["ms_per_labeling"]
+    res["random_over_standard_at_1.5pc"] = round(a / b, 3)
+    g = gen.bethe_random_regular(1 << 24, 3, 0.5, 3)
+    nn, oe = gen.ell_from_edges(g.n_sites, g.src, g.dst, g.occ, 3)
+    _, res["random3reg_2^24_p0.5"] = bench_ell(nn, oe, steps, warmup)
+    return res
 
 
 def probe_copy(nbytes=1 << 30):
@@ -597,6 +645,10 @@ def main():
             extra["serving"] = bench_serving(args.pool, args.requests, 5)
         except Exception as e:
             extra["serving"] = f"failed: {type(e).__name__}: {e}"
+        try:
+            extra["ell"] = bench_ell_set(args.steps, args.warmup)
+        except Exception as e:
+            extra["ell"] = f"failed: {type(e).__name__}: {e}"
         for pp in (0.45, 0.5, 0.55):
             b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
             _, rb = bench_edges(b, args.steps, args.warmup, cold=True)

@@ -81,6 +81,7 @@ def _L():
             "gen_shuffle_edges": (None, [u64, u32, i64, P, P]),
             "gen_random_orientation": (None, [u64, u32, i64, P, P]),
             "gen_mix_seed": (u64, [u64, u64]),
+            "gen_ell_from_edges": (ctypes.c_int, [i64, i64, P, P, P, i32, i32, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -269,6 +270,25 @@ def cayley_realization(shells: int, p: float, seed: int, random_position: bool) 
         randomize_positions(src, dst, n, seed)
     name = f"cayley G={shells} {'random' if random_position else 'standard'}"
     return EdgeGraph(n, src, dst, bernoulli(seed, len(src), p), name, p)
+
+
+def ell_from_edges(n: int, src: np.ndarray, dst: np.ndarray, occ: np.ndarray | None, z_max: int,
+                   pad: int = -1):
+    """The paper's padded, column-major neighbour list of an undirected bond
+    list (section 3): every bond (a, b) is entered in both a's and b's list
+    with the same occupancy, in bond order, unused slots `pad`.  Returns
+    (nn, occ_ell), both of shape (z_max, n): row k is slot k of every site
+    (occ_ell is None when occ is).  Raises ValueError when a site has more
+    than z_max neighbours."""
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    nn = np.empty((z_max, n), np.int32)
+    occ_ell = None if occ is None else np.empty((z_max, n), np.uint8)
+    o = None if occ is None else np.ascontiguousarray(occ, np.uint8)
+    if _L().gen_ell_from_edges(n, len(src), _p(src), _p(dst), None if o is None else _p(o), z_max, pad,
+                               _p(nn), None if occ_ell is None else _p(occ_ell)) != 0:
+        raise ValueError(f"a site has more than z_max = {z_max} neighbours")
+    return nn, occ_ell
 
 
 # the five workloads of the measurement plan

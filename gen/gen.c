@@ -451,3 +451,34 @@ uint64_t gen_mix_seed(uint64_t base, uint64_t k) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
+
+/* The paper's padded, column-major neighbour list (section 3) of an
+ * undirected bond list: bond b is entered in the lists of both its ends, in
+ * bond order, with occupancy occ[b] (1 when occ is NULL); slot k of site i is
+ * nn[k*n + i], unused slots hold `pad` (occupancy 0).  occ_ell may be NULL.
+ * Returns 0, or -1 when a site would need more than z_max slots. */
+int gen_ell_from_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                       const uint8_t* occ, int32_t z_max, int32_t pad, int32_t* nn,
+                       uint8_t* occ_ell) {
+  int32_t* fill = (int32_t*)calloc(n > 0 ? (size_t)n : 1, sizeof(int32_t));
+  if (!fill) return -1;
+  for (int64_t s = 0; s < n * (int64_t)z_max; ++s) {
+    nn[s] = pad;
+    if (occ_ell) occ_ell[s] = 0;
+  }
+  for (int64_t b = 0; b < m; ++b) {
+    const int32_t ends[2][2] = {{src[b], dst[b]}, {dst[b], src[b]}};
+    for (int e = 0; e < 2; ++e) {
+      const int32_t u = ends[e][0];
+      const int32_t k = fill[u]++;
+      if (k >= z_max) {
+        free(fill);
+        return -1;
+      }
+      nn[(int64_t)k * n + u] = ends[e][1];
+      if (occ_ell) occ_ell[(int64_t)k * n + u] = occ ? occ[b] : 1;
+    }
+  }
+  free(fill);
+  return 0;
+}

@@ -69,6 +69,26 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
                      const uint8_t* occupied, int32_t* labels_out, void* stream);
 
 /*
+ * Label the clusters of a graph given as the paper's padded neighbour list
+ * (section 3): z_max entries per site, column-major, so neighbour k of site
+ * i is nn_list[k*N + i].  Runs the paper's own four steps: (i) each site's
+ * label becomes its lowest occupied neighbour numbered below it (or its own
+ * id), (ii) analysis, (iii) label reduction with Algorithm 1 over the rest of
+ * each site's lower neighbours, (iv) analysis.
+ *   n_sites    N (0 <= N <= INT32_MAX)
+ *   z_max      entries per site (>= 0, N * z_max <= 2^40)
+ *   nn_list    device int32[z_max * N]; an entry outside [0, N) is padding.
+ *              A bond is seen from its higher-numbered end, so it must be
+ *              listed there (listing both ends, as the paper does, is fine)
+ *   occupied   device uint8[z_max * N] aligned with nn_list (nonzero =
+ *              occupied; both listings of a bond should agree), or NULL
+ *   labels_out device int32[N]: the minimum site id of each site's cluster
+ * Same results as ccl_label over the listed bonds.  Asynchronous on stream.
+ */
+ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
+                         const uint8_t* occupied, int32_t* labels_out, void* stream);
+
+/*
  * Workspace bytes ccl_label_csr needs: zero for n_sites <= 65536 (one tile),
  * else one 8-byte slot per bond (the bonds leaving their tile are collected
  * there) plus 8 bytes per 65536-site tile, rounded up to 256 bytes.

@@ -15,6 +15,10 @@ probability p (section 4).
   smaller, final find per site.
 * ``label_bfs``: breadth-first search in pure Python, the brute force the C
   oracle is pinned against on tiny graphs.
+* ``ell_init`` / ``ell_residual_left`` / ``analysis``: the paper's steps (i)
+  and (ii) on its neighbour list, in numpy, for the paper's statement that
+  standard numbering of the Bethe lattice leaves no residual list (so steps
+  (i) and (ii) alone give the final labels).
 * ``cluster_sizes`` / ``spans`` / ``mean_cluster_size`` / ``largest_fraction``:
   percolation observables (section 4) computed from a labeling with numpy.
 """
@@ -103,6 +107,42 @@ def label_ell(n_sites: int, z_max: int, nn, occ=None) -> np.ndarray:
     if _L().oracle_label_ell(n_sites, z_max, _p(nn), _p(occ), _p(out)) != 0:
         raise ValueError("oracle_label_ell: bad size or site id")
     return out
+
+
+def ell_init(n_sites: int, z_max: int, nn, occ=None) -> np.ndarray:
+    """Step (i) of the paper's schedule on its neighbour list (section 3):
+    each site's residual list holds its occupied neighbours numbered below
+    it; the site's label becomes the lowest of them (which leaves the list),
+    or the site itself when the list is empty."""
+    i = np.arange(n_sites, dtype=np.int64)
+    if z_max == 0 or n_sites == 0:
+        return i.astype(np.int32)
+    nn = np.asarray(nn, np.int64).reshape(z_max, n_sites)
+    on = np.ones(nn.shape, bool) if occ is None else np.asarray(occ).reshape(z_max, n_sites) != 0
+    lower = on & (nn >= 0) & (nn < i)
+    return np.where(lower, nn, i).min(axis=0).astype(np.int32)
+
+
+def ell_residual_left(n_sites: int, z_max: int, nn, occ=None) -> np.ndarray:
+    """Entries left on each site's residual list after step (i): its occupied
+    lower neighbours less the one step (i) took."""
+    if z_max == 0 or n_sites == 0:
+        return np.zeros(n_sites, np.int64)
+    i = np.arange(n_sites, dtype=np.int64)
+    nn = np.asarray(nn, np.int64).reshape(z_max, n_sites)
+    on = np.ones(nn.shape, bool) if occ is None else np.asarray(occ).reshape(z_max, n_sites) != 0
+    return np.maximum((on & (nn >= 0) & (nn < i)).sum(axis=0) - 1, 0)
+
+
+def analysis(label) -> np.ndarray:
+    """The paper's analysis step: label[i] = label[label[i]] for every site,
+    repeated until no label changes (section 3)."""
+    lab = np.array(label, np.int64)
+    while True:
+        nxt = lab[lab]
+        if np.array_equal(nxt, lab):
+            return lab.astype(np.int32)
+        lab = nxt
 
 
 def label_batched(site_off, bond_off, src, dst, occ=None, n_threads: int = 0) -> np.ndarray:

@@ -60,6 +60,7 @@ def _load():
         "ccl_label": (st, [i64, i64, P, P, P, P, P]),
         "ccl_label_csr_workspace_size": (sz, [i64, i64]),
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
+        "ccl_label_ell": (st, [i64, i32, P, P, P, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
         "ccl_plan_destroy": (st, [P]),
         "ccl_plan_get_tuning": (st, [P, P]),
@@ -130,6 +131,28 @@ def label(src: torch.Tensor, dst: torch.Tensor, n_sites: int, occ: torch.Tensor 
     pl = _dev_ptr(out, torch.int32, "out", n_sites, dev)
     with torch.cuda.device(dev):
         _check(_lib.ccl_label(n_sites, m, ps, pd, po, pl, _stream(stream, dev)), "ccl_label")
+    return out
+
+
+def label_ell(nn: torch.Tensor, occ: torch.Tensor | None = None, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """Min-site-index cluster labels from the paper's padded neighbour list:
+    `nn` is int32 of shape (z_max, n_sites), row k holding neighbour k of
+    every site (the column-major list, entries outside [0, n_sites) are
+    padding); `occ` is uint8 of the same shape or None (all occupied)."""
+    if nn.dim() != 2:
+        raise ValueError("nn must have shape (z_max, n_sites)")
+    dev = nn.device
+    z, n = nn.shape
+    pn = _dev_ptr(nn, torch.int32, "nn", None, dev)
+    po = _dev_ptr(occ, torch.uint8, "occ", nn.numel(), dev)
+    if occ is not None and occ.shape != nn.shape:
+        raise ValueError("occ must have the shape of nn")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    pl = _dev_ptr(out, torch.int32, "out", n, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label_ell(n, z, pn, po, pl, _stream(stream, dev)), "ccl_label_ell")
     return out
 
 

@@ -154,6 +154,24 @@ ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_pt
                           (hipStream_t)stream, *d);
 }
 
+ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
+                         const uint8_t* occupied, int32_t* labels_out, void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX || z_max < 0) return CCL_ERR_INVALID_VALUE;
+  // at most 2^40 list entries (4 TiB): more than any device holds, and the
+  // byte sizes below cannot overflow
+  if (z_max > 0 && n_sites > ((int64_t)1 << 40) / z_max) return CCL_ERR_INVALID_VALUE;
+  if (n_sites == 0) return CCL_OK;
+  if (labels_out == nullptr || (z_max > 0 && nn_list == nullptr)) return CCL_ERR_INVALID_VALUE;
+  const size_t lb = (size_t)n_sites * 4, eb = (size_t)n_sites * (size_t)z_max;
+  if (overlaps(labels_out, lb, nn_list, eb * 4) || overlaps(labels_out, lb, occupied, eb))
+    return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_label_ell(n_sites, z_max, nn_list, z_max > 0 ? occupied : nullptr, labels_out,
+                          (hipStream_t)stream, *d);
+}
+
 static ccl_status run_count(unsigned long long* n_bad, hipStream_t s,
                             ccl_status (*launch)(const void*, unsigned long long*, hipStream_t,
                                                  const DeviceInfo&),

@@ -96,6 +96,8 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
                             const uint8_t* occ, int32_t* label, void* workspace,
                             hipStream_t s, const DeviceInfo& d);
 size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds);
+ccl_status launch_label_ell(int64_t n, int32_t z, const int32_t* nn, const uint8_t* occ,
+                            int32_t* label, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                  unsigned long long* d_count, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_validate_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,

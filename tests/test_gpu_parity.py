@@ -48,6 +48,18 @@ def gpu_csr(ccl, row_ptr, col, occ=None):
     return out.cpu().numpy()
 
 
+def gpu_ell(ccl, nn, occ=None):
+    _say(f"ccl_label_ell n={nn.shape[1]} z_max={nn.shape[0]}")
+    out = ccl.label_ell(dev(nn), None if occ is None else dev(occ))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_ell(nn, occ=None):
+    z, n = nn.shape
+    return oracle.label_ell(n, z, nn.ravel(), None if occ is None else occ.ravel())
+
+
 # ------------------------------------------------------------ small graphs
 
 @pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
@@ -171,6 +183,70 @@ def test_csr_almost_affine(ccl):
     o = (rng.random(m) < 0.45).astype(np.uint8)
     np.testing.assert_array_equal(gpu_csr(ccl, rp, c, o), oracle.label_csr(n, rp, c, o))
     np.testing.assert_array_equal(gpu_csr(ccl, rp, c, None), oracle.label_csr(n, rp, c, None))
+
+
+# ------------------------------------------- the paper's neighbour-list path
+
+def test_ell_lattices_and_trees(ccl):
+    """ccl_label_ell (steps (i)-(iv) of section 3 on the padded column-major
+    neighbour list) against the oracle: a triangle lattice (z = 6) with and
+    without a mask, Cayley trees in standard and random position (z = 3),
+    and a random 3-regular graph."""
+    g = gen.triangle_realization(96, 0.3473, 12)
+    nn, oe = gen.ell_from_edges(g.n_sites, g.src, g.dst, g.occ, 6)
+    np.testing.assert_array_equal(gpu_ell(ccl, nn, oe), oracle_ell(nn, oe))
+    np.testing.assert_array_equal(gpu_ell(ccl, nn), oracle_ell(nn))
+    for rp in (False, True):
+        t = gen.cayley_realization(14, 0.75, 8, rp)
+        nn, oe = gen.ell_from_edges(t.n_sites, t.src, t.dst, t.occ, 3)
+        got = gpu_ell(ccl, nn, oe)
+        np.testing.assert_array_equal(got, oracle_ell(nn, oe))
+        assert len(np.unique(got)) == t.n_sites - int(t.occ.sum())  # a forest
+    r = gen.bethe_random_regular(1 << 18, 3, 0.5, 4)
+    nn, oe = gen.ell_from_edges(r.n_sites, r.src, r.dst, r.occ, 3)
+    np.testing.assert_array_equal(gpu_ell(ccl, nn, oe), oracle_ell(nn, oe))
+
+
+def test_ell_ragged_padding_and_degenerate(ccl):
+    # ragged lists with padding (-1), duplicates and self entries, each bond
+    # listed at both ends with one occupancy
+    rng = np.random.default_rng(31)
+    n, m = 20000, 45000
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    occ = (rng.random(m) < 0.55).astype(np.uint8)
+    z = int(np.bincount(np.concatenate([src, dst]), minlength=n).max())
+    nn, oe = gen.ell_from_edges(n, src, dst, occ, z + 2)
+    got = gpu_ell(ccl, nn, oe)
+    np.testing.assert_array_equal(got, oracle_ell(nn, oe))
+    np.testing.assert_array_equal(got, oracle.label_edges(n, src, dst, occ))
+    # z_max = 0, all padding, one site
+    np.testing.assert_array_equal(gpu_ell(ccl, np.zeros((0, 1000), np.int32)), np.arange(1000))
+    np.testing.assert_array_equal(gpu_ell(ccl, np.full((4, 777), -1, np.int32)), np.arange(777))
+    assert gpu_ell(ccl, np.zeros((1, 1), np.int32)).tolist() == [0]
+    out = ccl.label_ell(torch.zeros((3, 0), dtype=torch.int32, device="cuda"))
+    assert out.numel() == 0
+
+
+def test_ell_argument_errors(ccl):
+    import ctypes
+
+    lib = ccl._lib
+    lab = torch.empty(16, dtype=torch.int32, device="cuda")
+    nn = torch.zeros(16, dtype=torch.int32, device="cuda")
+    P = ctypes.c_void_p
+    s = P(torch.cuda.current_stream().cuda_stream)
+    INVALID = 1  # CCL_ERR_INVALID_VALUE
+    assert lib.ccl_label_ell(16, -1, P(nn.data_ptr()), None, P(lab.data_ptr()), s) == INVALID
+    assert lib.ccl_label_ell(16, 1, None, None, P(lab.data_ptr()), s) == INVALID
+    assert lib.ccl_label_ell(16, 1, P(nn.data_ptr()), None, None, s) == INVALID
+    assert lib.ccl_label_ell(1 << 31, 1, P(nn.data_ptr()), None, P(lab.data_ptr()), s) == INVALID
+    assert lib.ccl_label_ell(1 << 30, (1 << 31) - 1, P(nn.data_ptr()), None, P(lab.data_ptr()), s) == \
+        INVALID
+    # labels overlapping the list
+    assert lib.ccl_label_ell(16, 1, P(nn.data_ptr()), None, P(nn.data_ptr()), s) == INVALID
+    with pytest.raises(ValueError):
+        ccl.label_ell(nn)  # not two-dimensional
 
 
 @pytest.mark.parametrize("p", [0.45, 0.5, 0.55])

@@ -172,6 +172,68 @@ def test_csr_and_ell_forms_match_bfs():
     check_invariants(got, n, np.zeros(0, np.int32), np.zeros(0, np.int32), None)
 
 
+def test_ell_from_edges_round_trip():
+    g = gen.triangle_realization(7, 0.5, 4)
+    nn, oe = gen.ell_from_edges(g.n_sites, g.src, g.dst, g.occ, 6)
+    assert nn.shape == (6, g.n_sites) and (nn >= 0).all()  # every triangle site has six neighbours
+    back = {(min(int(nn[k, i]), i), max(int(nn[k, i]), i), int(oe[k, i]))
+            for k in range(6) for i in range(g.n_sites)}
+    want = {(min(int(a), int(b)), max(int(a), int(b)), int(o)) for a, b, o in zip(g.src, g.dst, g.occ)}
+    assert back == want
+    with pytest.raises(ValueError):
+        gen.ell_from_edges(g.n_sites, g.src, g.dst, g.occ, 5)
+
+
+@pytest.mark.parametrize("shells", [6, 9])
+@pytest.mark.parametrize("p", [0.25, 0.5, 0.75])
+def test_standard_cayley_leaves_no_residual_list(shells, p):
+    """Section 3.3 of the paper: with the Bethe lattice numbered from the
+    centre outward every residual list is empty after initialization, so
+    steps (i) and (ii) alone give the final labels; with random numbering
+    they do not."""
+    for random_position in (False, True):
+        g = gen.cayley_realization(shells, p, 5, random_position)
+        n = g.n_sites
+        nn, oe = gen.ell_from_edges(n, g.src, g.dst, g.occ, 3)
+        left = oracle.ell_residual_left(n, 3, nn, oe)
+        after_ii = oracle.analysis(oracle.ell_init(n, 3, nn, oe))
+        final = oracle.label_ell(n, 3, nn.ravel(), oe.ravel())
+        np.testing.assert_array_equal(final, oracle.label_edges(n, g.src, g.dst, g.occ))
+        if not random_position:
+            assert left.sum() == 0
+            np.testing.assert_array_equal(after_ii, final)
+        else:
+            assert left.sum() > 0
+            if p == 0.75:  # enough joins that step (iii) has work to do
+                assert not np.array_equal(after_ii, final)
+
+
+def test_ell_steps_i_ii_pinned():
+    """Step (i) points every site at a lower neighbour (or itself), so step
+    (ii) must give the minimum of each tree of that forest: the edge oracle
+    on the forest's edges.  Every label after (ii) is a root."""
+    rng = np.random.default_rng(17)
+    n, z = 400, 7
+    nn = rng.integers(-60, n, (z, n)).astype(np.int32)  # negatives are padding
+    occ = (rng.random((z, n)) < 0.6).astype(np.uint8)
+    init = oracle.ell_init(n, z, nn, occ)
+    i = np.arange(n)
+    assert (init <= i).all()
+    lower = (nn >= 0) & (nn < i) & (occ != 0)
+    assert ((init == i) == ~lower.any(axis=0)).all()
+    after = oracle.analysis(init)
+    assert (after[after] == after).all()
+    moved = init != i
+    np.testing.assert_array_equal(after, oracle.label_edges(n, i[moved].astype(np.int32), init[moved]))
+    # and the full schedule equals brute force on the bonds seen from their
+    # higher end (each listed bond here appears in one list only)
+    bonds = [(int(i_), int(nn[k, i_])) for k in range(z) for i_ in range(n) if lower[k, i_]]
+    want = oracle.label_bfs(n, bonds)
+    src = np.array([a for a, _ in bonds], np.int32)
+    dst = np.array([b for _, b in bonds], np.int32)
+    assert oracle.label_edges(n, src, dst).tolist() == want
+
+
 def test_csr_with_empty_rows_and_ragged_degrees():
     # honeycomb half-CSR has every B row empty
     L = 5
