@@ -98,6 +98,7 @@ def load_traffic(kernel: str, workload: str):
 COPY_PROBE_BYTES = 1 << 30  # the copy probe reads and writes this much
 KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
                 "k_ell_init": "ccl_ell_init", "k_ell_reduce": "ccl_ell_reduce",
+                "k_cluster_sizes": "ccl_cluster_sizes",
                 "k_flatten": "ccl_flatten", "k_flatten_window": "ccl_flatten_window",
                 "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
 
@@ -319,6 +320,57 @@ def bench_ell_set(steps, warmup, shells=22):
     g = gen.bethe_random_regular(1 << 24, 3, 0.5, 3)
     nn, oe = gen.ell_from_edges(g.n_sites, g.src, g.dst, g.occ, 3)
     _, res["random3reg_2^24_p0.5"] = bench_ell(nn, oe, steps, warmup)
+    return res
+
+
+def bench_stats(lab_headline, steps, samples=32, L=512):
+    """Cluster statistics on the GPU: the cost of sequential ids, sizes and
+    the spanning test on the headline labeling, and the spanning probability
+    R_span(p) of section 4 on cylinders (open top and bottom) of both
+    lattices around their thresholds, from GPU labelings."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    res = {}
+    n = lab_headline.numel()
+    side = int(round(n ** 0.5))
+    top = torch.arange(side, dtype=torch.int32, device="cuda")
+    bot = torch.arange(n - side, n, dtype=torch.int32, device="cuda")
+    with ccl.trace() as rec:
+        for _ in range(steps):
+            ccl.cluster_ids(lab_headline)
+            ccl.cluster_sizes(lab_headline)
+            ccl.spans(lab_headline, top, bot)
+        torch.cuda.synchronize()
+    agg = {}
+    for name, ms in rec:
+        agg.setdefault(name, []).append(ms)
+    res["headline_kernels_ms"] = {k: round(sum(v) / len(v), 5) for k, v in agg.items()}
+    _, count = ccl.cluster_ids(lab_headline)
+    res["headline_clusters"] = int(count.item())
+    for kind, pc in (("triangle", 0.3473), ("honeycomb", 0.6527)):
+        if kind == "triangle":
+            src, dst = gen.triangle_edges(L)
+            nn, wrap = L * L, gen.y_wrap_bonds_triangle(L)
+            row = np.arange(nn) // L
+        else:
+            src, dst = gen.honeycomb_edges(L)
+            nn, wrap = 2 * L * L, gen.y_wrap_bonds_honeycomb(L)
+            row = (np.arange(nn) // 2) // L
+        ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+        t = torch.from_numpy(np.nonzero(row == 0)[0].astype(np.int32)).cuda()
+        b = torch.from_numpy(np.nonzero(row == L - 1)[0].astype(np.int32)).cuda()
+        curve = {}
+        for p in (round(pc - 0.02, 4), pc, round(pc + 0.02, 4)):
+            hits = 0
+            for k in range(samples):
+                occ = gen.bernoulli(gen.mix_seed(1000 + k, 7), len(src), p)
+                occ[wrap] = 0
+                lab = ccl.label(ds, dd, nn, torch.from_numpy(occ).cuda())
+                hits += int(ccl.spans(lab, t, b).item())
+            curve[str(p)] = round(hits / samples, 4)
+        res[f"R_span_{kind}_L{L}"] = {"n_sites": nn, "samples": samples, "R_span": curve}
     return res
 
 
@@ -645,6 +697,10 @@ def main():
             extra["serving"] = bench_serving(args.pool, args.requests, 5)
         except Exception as e:
             extra["serving"] = f"failed: {type(e).__name__}: {e}"
+        try:
+            extra["cluster_statistics"] = bench_stats(out, args.steps)
+        except Exception as e:
+            extra["cluster_statistics"] = f"failed: {type(e).__name__}: {e}"
         try:
             extra["ell"] = bench_ell_set(args.steps, args.warmup)
         except Exception as e:

@@ -201,6 +201,53 @@ ccl_status ccl_label_batched_per_instance(int32_t n_inst, const int64_t* site_of
                                           const int32_t* dst, const uint8_t* occupied,
                                           int32_t* labels_out, void* stream);
 
+/* ------------------------------------------------- cluster statistics */
+
+/*
+ * These take a finished labeling (labels[i] = minimum site id of i's
+ * cluster, as every ccl_label* call returns); on anything else the results
+ * are undefined.  Asynchronous on `stream`; off the labeling path.  They
+ * serve the percolation application of section 4.
+ */
+
+/* Workspace bytes ccl_cluster_ids needs (4 per 4096 sites, at least 4). */
+size_t ccl_cluster_ids_workspace_size(int64_t n_sites);
+
+/*
+ * Sequential cluster ids, the renumbering the paper mentions at the end of
+ * section 3: the cluster whose minimum site is the k-th smallest cluster
+ * minimum gets id k.
+ *   ids_out         device int32[N]: ids_out[i] = id of i's cluster
+ *   n_clusters_out  device int32: the number of clusters
+ *   workspace       device buffer of ccl_cluster_ids_workspace_size(N)
+ *                   bytes, 4-byte aligned, contents need not be initialised
+ * No buffer may overlap another.
+ */
+ccl_status ccl_cluster_ids(int64_t n_sites, const int32_t* labels, int32_t* ids_out,
+                           int32_t* n_clusters_out, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/*
+ * Cluster sizes indexed by the cluster's minimum site: sizes_out[r] is the
+ * number of sites labelled r (zero where r is not a cluster minimum).
+ *   sizes_out  device int32[N], overwritten
+ */
+ccl_status ccl_cluster_sizes(int64_t n_sites, const int32_t* labels, int32_t* sizes_out,
+                             void* stream);
+
+/*
+ * The spanning test of section 4: *result_out = 1 when one cluster holds a
+ * site of sites_a and a site of sites_b (e.g. the first and the last row of a
+ * lattice), else 0.
+ *   sites_a, sites_b  device int32[n_a], int32[n_b], ids in [0, N)
+ *   flags             device uint8[N] workspace, contents need not be
+ *                     initialised
+ *   result_out        device int32
+ */
+ccl_status ccl_spans(int64_t n_sites, const int32_t* labels, int64_t n_a, const int32_t* sites_a,
+                     int64_t n_b, const int32_t* sites_b, uint8_t* flags, int32_t* result_out,
+                     void* stream);
+
 /* ---------------------------------------------------------------- checks */
 
 /*

@@ -19,8 +19,10 @@ probability p (section 4).
   and (ii) on its neighbour list, in numpy, for the paper's statement that
   standard numbering of the Bethe lattice leaves no residual list (so steps
   (i) and (ii) alone give the final labels).
-* ``cluster_sizes`` / ``spans`` / ``mean_cluster_size`` / ``largest_fraction``:
-  percolation observables (section 4) computed from a labeling with numpy.
+* ``cluster_sizes`` / ``sizes_by_minimum`` / ``cluster_ids`` / ``spans`` /
+  ``mean_cluster_size`` / ``largest_fraction``: percolation observables
+  (section 4) and the sequential renumbering (section 3) computed from a
+  labeling with numpy.
 """
 from __future__ import annotations
 
@@ -188,6 +190,19 @@ def cluster_sizes(labels: np.ndarray) -> np.ndarray:
     """Size of every cluster (one entry per root)."""
     counts = np.bincount(labels.astype(np.int64), minlength=len(labels))
     return counts[counts > 0]
+
+
+def sizes_by_minimum(labels: np.ndarray) -> np.ndarray:
+    """sizes[r] = number of sites labelled r: each cluster's size at its
+    minimum site, zero elsewhere."""
+    return np.bincount(np.asarray(labels, np.int64), minlength=len(labels)).astype(np.int32)
+
+
+def cluster_ids(labels: np.ndarray):
+    """Sequential cluster ids (section 3, last paragraph): clusters numbered
+    0, 1, ... in the order of their minimum site.  Returns (ids, count)."""
+    uniq, inv = np.unique(np.asarray(labels, np.int64), return_inverse=True)
+    return inv.astype(np.int32), int(uniq.size)
 
 
 def mean_cluster_size(labels: np.ndarray) -> float:

@@ -61,6 +61,10 @@ def _load():
         "ccl_label_csr_workspace_size": (sz, [i64, i64]),
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
         "ccl_label_ell": (st, [i64, i32, P, P, P, P]),
+        "ccl_cluster_ids_workspace_size": (sz, [i64]),
+        "ccl_cluster_ids": (st, [i64, P, P, P, P, sz, P]),
+        "ccl_cluster_sizes": (st, [i64, P, P, P]),
+        "ccl_spans": (st, [i64, P, i64, P, i64, P, P, P, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
         "ccl_plan_destroy": (st, [P]),
         "ccl_plan_get_tuning": (st, [P, P]),
@@ -154,6 +158,55 @@ def label_ell(nn: torch.Tensor, occ: torch.Tensor | None = None, out: torch.Tens
     with torch.cuda.device(dev):
         _check(_lib.ccl_label_ell(n, z, pn, po, pl, _stream(stream, dev)), "ccl_label_ell")
     return out
+
+
+def cluster_ids(labels: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Sequential cluster ids of a finished labeling (the k-th smallest
+    cluster minimum gets id k) and the number of clusters, a 1-element int32
+    GPU tensor (read it when the stream is done)."""
+    dev = labels.device
+    n = labels.numel()
+    pl = _dev_ptr(labels, torch.int32, "labels", None, dev)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    po = _dev_ptr(out, torch.int32, "out", n, dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(int(_lib.ccl_cluster_ids_workspace_size(n)), 4), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_cluster_ids(n, pl, po, _dev_ptr(count, torch.int32, "count"),
+                                    _dev_ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream, dev)),
+               "ccl_cluster_ids")
+    return out, count
+
+
+def cluster_sizes(labels: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """sizes[r] = number of sites labelled r (zero unless r is a cluster minimum)."""
+    dev = labels.device
+    n = labels.numel()
+    pl = _dev_ptr(labels, torch.int32, "labels", None, dev)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    po = _dev_ptr(out, torch.int32, "out", n, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_cluster_sizes(n, pl, po, _stream(stream, dev)), "ccl_cluster_sizes")
+    return out
+
+
+def spans(labels: torch.Tensor, sites_a: torch.Tensor, sites_b: torch.Tensor, stream=None) -> torch.Tensor:
+    """1-element int32 GPU tensor: 1 when one cluster holds a site of sites_a
+    and one of sites_b (the spanning test of section 4)."""
+    dev = labels.device
+    n = labels.numel()
+    pl = _dev_ptr(labels, torch.int32, "labels", None, dev)
+    pa = _dev_ptr(sites_a, torch.int32, "sites_a", None, dev)
+    pb = _dev_ptr(sites_b, torch.int32, "sites_b", None, dev)
+    flags = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    res = torch.empty(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_spans(n, pl, sites_a.numel(), pa, sites_b.numel(), pb,
+                              _dev_ptr(flags, torch.uint8, "flags"), _dev_ptr(res, torch.int32, "res"),
+                              _stream(stream, dev)), "ccl_spans")
+    return res
 
 
 def csr_workspace_bytes(n_sites: int, n_bonds: int) -> int:

@@ -172,6 +172,62 @@ ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
                           (hipStream_t)stream, *d);
 }
 
+size_t ccl_cluster_ids_workspace_size(int64_t n_sites) {
+  return n_sites > 0 ? cluster_ids_workspace_bytes(n_sites) : 0;
+}
+
+ccl_status ccl_cluster_ids(int64_t n_sites, const int32_t* labels, int32_t* ids_out,
+                           int32_t* n_clusters_out, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX) return CCL_ERR_INVALID_VALUE;
+  if (n_sites == 0) return CCL_OK;
+  const size_t need = cluster_ids_workspace_bytes(n_sites), lb = (size_t)n_sites * 4;
+  if (!labels || !ids_out || !n_clusters_out || !workspace || workspace_bytes < need ||
+      ((uintptr_t)workspace & 3) != 0)
+    return CCL_ERR_INVALID_VALUE;
+  if (overlaps(labels, lb, ids_out, lb) || overlaps(labels, lb, workspace, need) ||
+      overlaps(ids_out, lb, workspace, need) || overlaps(n_clusters_out, 4, labels, lb) ||
+      overlaps(n_clusters_out, 4, ids_out, lb) || overlaps(n_clusters_out, 4, workspace, need))
+    return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_cluster_ids(n_sites, labels, ids_out, n_clusters_out, workspace, (hipStream_t)stream,
+                            *d);
+}
+
+ccl_status ccl_cluster_sizes(int64_t n_sites, const int32_t* labels, int32_t* sizes_out,
+                             void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX) return CCL_ERR_INVALID_VALUE;
+  if (n_sites == 0) return CCL_OK;
+  const size_t lb = (size_t)n_sites * 4;
+  if (!labels || !sizes_out || overlaps(labels, lb, sizes_out, lb)) return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_cluster_sizes(n_sites, labels, sizes_out, (hipStream_t)stream, *d);
+}
+
+ccl_status ccl_spans(int64_t n_sites, const int32_t* labels, int64_t n_a, const int32_t* sites_a,
+                     int64_t n_b, const int32_t* sites_b, uint8_t* flags, int32_t* result_out,
+                     void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX || n_a < 0 || n_b < 0) return CCL_ERR_INVALID_VALUE;
+  if (!result_out) return CCL_ERR_INVALID_VALUE;
+  if ((n_a > 0 || n_b > 0) && n_sites == 0) return CCL_ERR_INVALID_VALUE;  // no valid ids
+  if (n_sites > 0 && (!labels || !flags)) return CCL_ERR_INVALID_VALUE;
+  if ((n_a > 0 && !sites_a) || (n_b > 0 && !sites_b)) return CCL_ERR_INVALID_VALUE;
+  const size_t lb = (size_t)n_sites * 4, fb = (size_t)n_sites;
+  if (overlaps(flags, fb, labels, lb) || overlaps(flags, fb, sites_a, (size_t)n_a * 4) ||
+      overlaps(flags, fb, sites_b, (size_t)n_b * 4) || overlaps(result_out, 4, flags, fb) ||
+      overlaps(result_out, 4, labels, lb))
+    return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_spans(n_sites, labels, n_a, sites_a, n_b, sites_b, flags, result_out,
+                      (hipStream_t)stream, *d);
+}
+
 static ccl_status run_count(unsigned long long* n_bad, hipStream_t s,
                             ccl_status (*launch)(const void*, unsigned long long*, hipStream_t,
                                                  const DeviceInfo&),

@@ -98,6 +98,14 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
 size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds);
 ccl_status launch_label_ell(int64_t n, int32_t z, const int32_t* nn, const uint8_t* occ,
                             int32_t* label, hipStream_t s, const DeviceInfo& d);
+size_t cluster_ids_workspace_bytes(int64_t n);
+ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int32_t* n_clusters,
+                              void* workspace, hipStream_t s, const DeviceInfo& d);
+ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes, hipStream_t s,
+                                const DeviceInfo& d);
+ccl_status launch_spans(int64_t n, const int32_t* label, int64_t n_a, const int32_t* a, int64_t n_b,
+                        const int32_t* b, uint8_t* flags, int32_t* result, hipStream_t s,
+                        const DeviceInfo& d);
 ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                  unsigned long long* d_count, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_validate_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,

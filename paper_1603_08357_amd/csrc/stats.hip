@@ -1,0 +1,245 @@
+// Cluster statistics of a finished labeling (label[i] = minimum site id of
+// i's cluster), for the percolation application of section 4:
+//   * sequential cluster ids (the renumbering the paper points to at the end
+//     of section 3): the k-th smallest cluster minimum gets id k;
+//   * cluster sizes, indexed by the cluster's minimum site;
+//   * the spanning test: does one cluster hold a site of set A and one of B.
+// A site i is its cluster's minimum exactly when label[i] == i.
+#include "common.hpp"
+
+namespace ccl {
+
+// ---------------------------------------------------------------- ids
+
+constexpr int kIdBlock = 1024;
+constexpr int kIdPer = 4;                        // sites per lane
+constexpr int kIdSpan = kIdBlock * kIdPer;       // sites per workgroup
+
+// Inclusive prefix sum of v over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix of v over the workgroup (kIdBlock lanes); *total gets the
+// sum.  `scratch` holds one word per wavefront.
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* scratch, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kWaves = kIdBlock / 64;
+  const uint32_t inc = wave_inclusive_sum(v);
+  if (lane == 63) scratch[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t w = lane < kWaves ? scratch[lane] : 0u;
+    const uint32_t wi = wave_inclusive_sum(w);
+    if (lane < kWaves) scratch[lane] = wi - w;  // exclusive per wavefront
+    if (lane == kWaves - 1) scratch[kWaves] = wi;
+  }
+  __syncthreads();
+  const uint32_t r = scratch[wave] + inc - v;
+  *total = scratch[kWaves];
+  __syncthreads();  // scratch is reused by the caller's next call
+  return r;
+}
+
+// ids[i] = number of cluster minima before i within the workgroup's span;
+// the span's count goes to part[block].
+__global__ void __launch_bounds__(kIdBlock)
+    k_ids_local(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ ids,
+                int32_t* __restrict__ part) {
+  __shared__ uint32_t scratch[kIdBlock / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kIdSpan + (int64_t)threadIdx.x * kIdPer;
+  uint32_t f[kIdPer], s = 0;
+#pragma unroll
+  for (int k = 0; k < kIdPer; ++k) {
+    const int64_t i = base + k;
+    f[k] = (i < n && label[i] == (int32_t)i) ? 1u : 0u;
+    s += f[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_sum(s, scratch, &total);
+#pragma unroll
+  for (int k = 0; k < kIdPer; ++k) {
+    const int64_t i = base + k;
+    if (i < n) ids[i] = (int32_t)run;
+    run += f[k];
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = (int32_t)total;
+}
+
+// Exclusive scan of the per-workgroup counts, in one workgroup, chunk by
+// chunk; the total is the number of clusters.
+__global__ void __launch_bounds__(kIdBlock)
+    k_ids_parts(int64_t n_parts, int32_t* __restrict__ part, int32_t* __restrict__ n_clusters) {
+  __shared__ uint32_t scratch[kIdBlock / 64 + 1];
+  uint32_t carry = 0;
+  for (int64_t c = 0; c < n_parts; c += kIdBlock) {
+    const int64_t j = c + threadIdx.x;
+    const uint32_t v = j < n_parts ? (uint32_t)part[j] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_sum(v, scratch, &total);
+    if (j < n_parts) part[j] = (int32_t)(carry + ex);
+    carry += total;
+  }
+  if (threadIdx.x == 0) *n_clusters = (int32_t)carry;
+}
+
+// Adds each span's offset: ids[i] becomes the number of minima before i.
+__global__ void __launch_bounds__(kIdBlock)
+    k_ids_offset(int64_t n, const int32_t* __restrict__ part, int32_t* __restrict__ ids) {
+  const int64_t base = (int64_t)blockIdx.x * kIdSpan + (int64_t)threadIdx.x * kIdPer;
+  const int32_t off = part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kIdPer; ++k)
+    if (base + k < n) ids[base + k] += off;
+}
+
+// ids[i] = ids[label[i]]: a minimum's entry is its own id and is rewritten
+// with the same value, and only minima are read, so this is done in place.
+__global__ void __launch_bounds__(kIdBlock)
+    k_ids_gather(int64_t n, const int32_t* __restrict__ label, int32_t* ids) {
+  const int64_t stride = (int64_t)gridDim.x * kIdBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kIdBlock + threadIdx.x; i < n; i += stride)
+    ids[i] = ids[label[i]];
+}
+
+size_t cluster_ids_workspace_bytes(int64_t n) {
+  const int64_t parts = (n + kIdSpan - 1) / kIdSpan;
+  return (size_t)(parts > 0 ? parts : 1) * sizeof(int32_t);
+}
+
+ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int32_t* n_clusters,
+                              void* workspace, hipStream_t s, const DeviceInfo& d) {
+  const int64_t parts = (n + kIdSpan - 1) / kIdSpan;
+  int32_t* part = static_cast<int32_t*>(workspace);
+  CCL_LAUNCH("ccl_ids_local", k_ids_local, (unsigned)parts, kIdBlock, 0, s, n, label, ids, part);
+  CCL_LAUNCH("ccl_ids_parts", k_ids_parts, 1u, kIdBlock, 0, s, parts, part, n_clusters);
+  CCL_LAUNCH("ccl_ids_offset", k_ids_offset, (unsigned)parts, kIdBlock, 0, s, n, part, ids);
+  CCL_LAUNCH("ccl_ids_gather", k_ids_gather, grid_for(n, kIdBlock, 8, d), kIdBlock, 0, s, n, label,
+             ids);
+  return CCL_OK;
+}
+
+// ---------------------------------------------------------------- sizes
+
+// Sizes are counted per workgroup in an LDS table (open addressing on the
+// cluster minimum; a workgroup's span of kSzSpan sites has at most that many
+// distinct labels, so the table of twice as many slots never fills), runs
+// of equal labels inside a lane first, then one global atomic per distinct
+// label and workgroup: a cluster spanning the whole graph costs one atomic
+// per workgroup, not one per site.
+constexpr int kSzBlock = 512;
+constexpr int kSzPer = 8;
+constexpr int kSzSpan = kSzBlock * kSzPer;
+constexpr int kSzSlots = 2 * kSzSpan;
+static_assert((kSzSlots & (kSzSlots - 1)) == 0, "power of two");
+
+__global__ void __launch_bounds__(kSzBlock) k_fill_zero(int64_t n, int32_t* __restrict__ a) {
+  const int64_t stride = (int64_t)gridDim.x * kSzBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kSzBlock + threadIdx.x; i < n; i += stride) a[i] = 0;
+}
+
+__global__ void __launch_bounds__(kSzBlock)
+    k_cluster_sizes(int64_t n, const int32_t* __restrict__ label, int32_t* sizes) {
+  __shared__ int32_t key[kSzSlots];
+  __shared__ uint32_t cnt[kSzSlots];
+  for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock) {
+    key[t] = -1;
+    cnt[t] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSzSpan + (int64_t)threadIdx.x * kSzPer;
+  int32_t cur = -1;
+  uint32_t run = 0;
+  auto add = [&](int32_t r, uint32_t c) {
+    uint32_t h = ((uint32_t)r * 2654435761u) & (kSzSlots - 1);
+    for (;;) {
+      int32_t seen = -1;
+      if (__hip_atomic_compare_exchange_strong(&key[h], &seen, r, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP) ||
+          seen == r) {
+        __hip_atomic_fetch_add(&cnt[h], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+      }
+      h = (h + 1) & (kSzSlots - 1);
+    }
+  };
+  for (int k = 0; k < kSzPer; ++k) {
+    const int64_t i = base + k;
+    if (i >= n) break;
+    const int32_t r = label[i];
+    if (r == cur) {
+      ++run;
+    } else {
+      if (run) add(cur, run);
+      cur = r;
+      run = 1;
+    }
+  }
+  if (run) add(cur, run);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock)
+    if (key[t] >= 0) atomicAdd(sizes + key[t], (int32_t)cnt[t]);
+}
+
+ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes, hipStream_t s,
+                                const DeviceInfo& d) {
+  CCL_LAUNCH("ccl_fill_zero", k_fill_zero, grid_for(n, kSzBlock, 8, d), kSzBlock, 0, s, n, sizes);
+  CCL_LAUNCH("ccl_cluster_sizes", k_cluster_sizes, (unsigned)((n + kSzSpan - 1) / kSzSpan), kSzBlock,
+             0, s, n, label, sizes);
+  return CCL_OK;
+}
+
+// ---------------------------------------------------------------- spanning
+
+// flags[label[a]] = 1 for every site a of A; then any site b of B whose
+// cluster is flagged sets *result.  Flag stores are plain byte stores of the
+// same value (races are benign); the flag array is cleared by a kernel, so
+// the sequence can be captured in a graph.
+constexpr int kSpBlock = 256;
+
+__global__ void __launch_bounds__(kSpBlock)
+    k_span_clear(int64_t n, uint8_t* __restrict__ flags, int32_t* __restrict__ result) {
+  const int64_t stride = (int64_t)gridDim.x * kSpBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += stride) flags[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *result = 0;
+}
+
+__global__ void __launch_bounds__(kSpBlock)
+    k_span_mark(int64_t n_a, const int32_t* __restrict__ a, const int32_t* __restrict__ label,
+                uint8_t* __restrict__ flags) {
+  const int64_t stride = (int64_t)gridDim.x * kSpBlock;
+  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_a; j += stride)
+    flags[label[a[j]]] = 1;
+}
+
+__global__ void __launch_bounds__(kSpBlock)
+    k_span_test(int64_t n_b, const int32_t* __restrict__ b, const int32_t* __restrict__ label,
+                const uint8_t* __restrict__ flags, int32_t* __restrict__ result) {
+  const int64_t stride = (int64_t)gridDim.x * kSpBlock;
+  bool hit = false;
+  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_b; j += stride)
+    hit = hit || flags[label[b[j]]] != 0;
+  if (__any(hit) && (threadIdx.x & 63) == 0) *result = 1;
+}
+
+ccl_status launch_spans(int64_t n, const int32_t* label, int64_t n_a, const int32_t* a, int64_t n_b,
+                        const int32_t* b, uint8_t* flags, int32_t* result, hipStream_t s,
+                        const DeviceInfo& d) {
+  CCL_LAUNCH("ccl_span_clear", k_span_clear, grid_for(n, kSpBlock, 8, d), kSpBlock, 0, s, n, flags,
+             result);
+  if (n_a > 0 && n_b > 0) {
+    CCL_LAUNCH("ccl_span_mark", k_span_mark, grid_for(n_a, kSpBlock, 8, d), kSpBlock, 0, s, n_a, a,
+               label, flags);
+    CCL_LAUNCH("ccl_span_test", k_span_test, grid_for(n_b, kSpBlock, 8, d), kSpBlock, 0, s, n_b, b,
+               label, flags, result);
+  }
+  return CCL_OK;
+}
+
+}  // namespace ccl

@@ -185,6 +185,59 @@ def test_csr_almost_affine(ccl):
     np.testing.assert_array_equal(gpu_csr(ccl, rp, c, None), oracle.label_csr(n, rp, c, None))
 
 
+# ------------------------------------------------------- cluster statistics
+
+def _gpu_stats(ccl, lab_t, top, bot):
+    ids, count = ccl.cluster_ids(lab_t)
+    sizes = ccl.cluster_sizes(lab_t)
+    sp = ccl.spans(lab_t, dev(top), dev(bot))
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), int(count.item()), sizes.cpu().numpy(), bool(sp.item())
+
+
+def test_cluster_statistics(ccl):
+    """Sequential ids, sizes at the cluster minima and the spanning test
+    against the oracle: triangle cylinders (open top and bottom) below, at
+    and above the threshold, a multi-tile CSR labeling, and degenerate
+    labelings."""
+    L = 256
+    n = L * L
+    src, dst = gen.triangle_edges(L)
+    wrap = gen.y_wrap_bonds_triangle(L)
+    top = np.arange(L, dtype=np.int32)
+    bot = np.arange(n - L, n, dtype=np.int32)
+    seen = set()
+    for p in (0.30, 0.3473, 0.40):
+        occ = gen.bernoulli(41, len(src), p)
+        occ[wrap] = 0
+        lab = oracle.label_edges(n, src, dst, occ)
+        _say(f"cluster statistics triangle L={L} p={p}")
+        lab_t = dev(lab)
+        ids, count, sizes, sp = _gpu_stats(ccl, lab_t, top, bot)
+        want_ids, want_count = oracle.cluster_ids(lab)
+        np.testing.assert_array_equal(ids, want_ids)
+        assert count == want_count
+        np.testing.assert_array_equal(sizes, oracle.sizes_by_minimum(lab))
+        assert sp == oracle.spans(lab, top, bot)
+        seen.add(sp)
+    assert seen == {False, True}  # both outcomes occur
+    g = gen.triangle_csr_realization(700, 0.3473, 3)
+    lab_t = ccl.label_csr(dev(g.row_ptr), dev(g.col), dev(g.occ))
+    lab = lab_t.cpu().numpy()
+    ids, count, sizes, _ = _gpu_stats(ccl, lab_t, top, bot)
+    np.testing.assert_array_equal(ids, oracle.cluster_ids(lab)[0])
+    np.testing.assert_array_equal(sizes, oracle.sizes_by_minimum(lab))
+    # isolated sites; one cluster; one site; empty site sets
+    for lab in (np.arange(5000, dtype=np.int32), np.zeros(70000, np.int32), np.zeros(1, np.int32)):
+        ids, count, sizes, sp = _gpu_stats(ccl, dev(lab), np.zeros(1, np.int32), np.zeros(1, np.int32))
+        np.testing.assert_array_equal(ids, oracle.cluster_ids(lab)[0])
+        assert count == oracle.cluster_ids(lab)[1]
+        np.testing.assert_array_equal(sizes, oracle.sizes_by_minimum(lab))
+        assert sp
+    e = torch.zeros(0, dtype=torch.int32, device="cuda")
+    assert ccl.spans(dev(np.arange(10, dtype=np.int32)), e, dev(np.arange(3, dtype=np.int32))).item() == 0
+
+
 # ------------------------------------------- the paper's neighbour-list path
 
 def test_ell_lattices_and_trees(ccl):

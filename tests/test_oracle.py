@@ -234,6 +234,26 @@ def test_ell_steps_i_ii_pinned():
     assert oracle.label_edges(n, src, dst).tolist() == want
 
 
+def test_cluster_statistics_pinned():
+    """Sequential ids: consecutive from 0, ordered like the cluster minima,
+    equal exactly within a cluster; sizes at the minima sum to N and match
+    the ids' histogram; brute force on a small lattice."""
+    g = gen.triangle_realization(12, 0.3473, 21)
+    lab = oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)
+    ids, count = oracle.cluster_ids(lab)
+    mins = np.flatnonzero(lab == np.arange(g.n_sites))
+    assert count == mins.size
+    np.testing.assert_array_equal(ids[mins], np.arange(count))  # k-th smallest minimum -> k
+    assert ((ids[:, None] == ids[None, :]) == (lab[:, None] == lab[None, :])).all()
+    sizes = oracle.sizes_by_minimum(lab)
+    assert sizes.sum() == g.n_sites and (sizes[mins] > 0).all() and (np.delete(sizes, mins) == 0).all()
+    np.testing.assert_array_equal(sizes[mins], np.bincount(ids))
+    np.testing.assert_array_equal(sizes[mins], oracle.cluster_sizes(lab))
+    clusters = oracle.label_bfs(g.n_sites, [(int(a), int(b)) for a, b, o in zip(g.src, g.dst, g.occ) if o])
+    for r in mins:
+        assert sizes[r] == clusters.count(int(r))
+
+
 def test_csr_with_empty_rows_and_ragged_degrees():
     # honeycomb half-CSR has every B row empty
     L = 5
