@@ -374,6 +374,82 @@ def bench_stats(lab_headline, steps, samples=32, L=512):
     return res
 
 
+def bench_monte_carlo(L, p, seed, steps, warmup):
+    """Realizations per second of the headline workload with each
+    realization's occupancy drawn on the device (ccl_bernoulli, the same
+    Philox stream the host generator uses) before it is labelled: nothing
+    crosses PCIe inside the loop."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    row_ptr, col = gen.triangle_csr(L)
+    n, m = L * L, len(col)
+    rp, dc = torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda()
+    occ = torch.empty(m, dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    k = [0]
+
+    def one():
+        ccl.bernoulli(gen.mix_seed(seed, k[0]), gen.STREAM_OCC, m, p, out=occ, stream=stream)
+        ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream)
+        k[0] += 1
+
+    ms, _ = time_steps(one, steps, warmup, stream)
+    kern = traced_kernels(one, steps)
+    # the device draws what the host generator draws (a prefix, bit for bit)
+    ccl.bernoulli(gen.mix_seed(seed, 0), gen.STREAM_OCC, m, p, out=occ, stream=stream)
+    head = occ[: 1 << 22].cpu().numpy()
+    same = bool(np.array_equal(head, gen.bernoulli(gen.mix_seed(seed, 0), 1 << 22, p)))
+    return {"ms_per_realization": round(ms, 5), "realizations_per_s": round(1e3 / ms, 1),
+            "kernels": {k_: round(v["mean_ms"], 5) for k_, v in kern.items()},
+            "device_mask_equals_host_generator": same}
+
+
+def bench_rspan_full(samples):
+    """R_span(p) of section 4 at the largest size class of Figs. 5-6 (triangle
+    L = 4096: 2^24 sites; honeycomb L = 2048: 2^23 sites), cylinders with open
+    top and bottom, occupancy drawn on the device, labelled on the GPU."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    res = {}
+    for kind, L, pc in (("triangle", 4096, 0.3473), ("honeycomb", 2048, 0.6527)):
+        if kind == "triangle":
+            src, dst = gen.triangle_edges(L)
+            n, wrap = L * L, gen.y_wrap_bonds_triangle(L)
+            row = np.arange(n) // L
+        else:
+            src, dst = gen.honeycomb_edges(L)
+            n, wrap = 2 * L * L, gen.y_wrap_bonds_honeycomb(L)
+            row = (np.arange(n) // 2) // L
+        ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+        dwrap = torch.from_numpy(np.nonzero(wrap)[0]).cuda()
+        top = torch.from_numpy(np.nonzero(row == 0)[0].astype(np.int32)).cuda()
+        bot = torch.from_numpy(np.nonzero(row == L - 1)[0].astype(np.int32)).cuda()
+        occ = torch.empty(len(src), dtype=torch.uint8, device="cuda")
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        curve = {}
+        t0 = time.perf_counter()
+        for dp in (-0.004, -0.002, 0.0, 0.002, 0.004):
+            p = round(pc + dp, 4)
+            hits = 0
+            for r in range(samples):
+                ccl.bernoulli(gen.mix_seed(9000 + r, int(p * 1e4)), gen.STREAM_OCC, len(src), p, out=occ)
+                occ.index_fill_(0, dwrap, 0)
+                ccl.label(ds, dd, n, occ, out=lab)
+                hits += int(ccl.spans(lab, top, bot).item())
+            curve[str(p)] = round(hits / samples, 4)
+        res[f"{kind}_L{L}"] = {"n_sites": n, "samples_per_p": samples, "R_span": curve,
+                               "seconds": round(time.perf_counter() - t0, 2)}
+        del ds, dd, occ, lab
+        torch.cuda.empty_cache()
+    return res
+
+
 def probe_copy(nbytes=1 << 30):
     """One plain copy of known size: calibrates the traffic counters."""
     import torch
@@ -697,6 +773,14 @@ def main():
             extra["serving"] = bench_serving(args.pool, args.requests, 5)
         except Exception as e:
             extra["serving"] = f"failed: {type(e).__name__}: {e}"
+        try:
+            extra["monte_carlo"] = bench_monte_carlo(args.L, args.p, args.seed, args.steps, args.warmup)
+        except Exception as e:
+            extra["monte_carlo"] = f"failed: {type(e).__name__}: {e}"
+        try:
+            extra["R_span_full_size"] = bench_rspan_full(64)
+        except Exception as e:
+            extra["R_span_full_size"] = f"failed: {type(e).__name__}: {e}"
         try:
             extra["cluster_statistics"] = bench_stats(out, args.steps)
         except Exception as e:

@@ -201,6 +201,25 @@ ccl_status ccl_label_batched_per_instance(int32_t n_inst, const int64_t* site_of
                                           const int32_t* dst, const uint8_t* occupied,
                                           int32_t* labels_out, void* stream);
 
+/* ------------------------------------------------- occupancy on the device */
+
+/*
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based
+ * generator used here in place of the paper's cuRAND draws (section 4).
+ * Word w of stream `stream_id` under `seed` is output word w mod 4 of the
+ * block with counter (b mod 2^32, b div 2^32, stream_id, 0), b = w div 4, and
+ * key (seed mod 2^32, seed div 2^32).
+ *   ccl_philox_u32: out[i] = word first + i, for i < n (device uint32[n])
+ *   ccl_bernoulli:  out[i] = 1 when word first + i < floor(p 2^32) (every
+ *                   bond when p >= 1, none when p <= 0), else 0 (device
+ *                   uint8[n]): bond occupancy with probability p
+ * n >= 0, first + n must not exceed 2^64.  Asynchronous on `stream`.
+ */
+ccl_status ccl_philox_u32(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n,
+                          uint32_t* out, void* stream);
+ccl_status ccl_bernoulli(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n, double p,
+                         uint8_t* out, void* stream);
+
 /* ------------------------------------------------- cluster statistics */
 
 /*

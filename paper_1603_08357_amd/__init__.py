@@ -61,6 +61,9 @@ def _load():
         "ccl_label_csr_workspace_size": (sz, [i64, i64]),
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
         "ccl_label_ell": (st, [i64, i32, P, P, P, P]),
+        "ccl_philox_u32": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, P, P]),
+        "ccl_bernoulli": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, ctypes.c_double,
+                               P, P]),
         "ccl_cluster_ids_workspace_size": (sz, [i64]),
         "ccl_cluster_ids": (st, [i64, P, P, P, P, sz, P]),
         "ccl_cluster_sizes": (st, [i64, P, P, P]),
@@ -157,6 +160,35 @@ def label_ell(nn: torch.Tensor, occ: torch.Tensor | None = None, out: torch.Tens
     pl = _dev_ptr(out, torch.int32, "out", n, dev)
     with torch.cuda.device(dev):
         _check(_lib.ccl_label_ell(n, z, pn, po, pl, _stream(stream, dev)), "ccl_label_ell")
+    return out
+
+
+def philox_u32(seed: int, stream_id: int, n: int, first: int = 0, out: torch.Tensor | None = None,
+               device=None, stream=None) -> torch.Tensor:
+    """Words first .. first+n-1 of Philox4x32-10 stream `stream_id` under
+    `seed`, drawn on the GPU (int32 tensor holding the uint32 bits)."""
+    dev = torch.device(device) if device is not None else (out.device if out is not None
+                                                          else torch.device("cuda", torch.cuda.current_device()))
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    po = _dev_ptr(out, torch.int32, "out", n, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_philox_u32(seed, stream_id, first, n, po, _stream(stream, dev)), "ccl_philox_u32")
+    return out
+
+
+def bernoulli(seed: int, stream_id: int, n: int, p: float, first: int = 0,
+              out: torch.Tensor | None = None, device=None, stream=None) -> torch.Tensor:
+    """Bond occupancy drawn on the GPU: out[i] = 1 when word first+i of the
+    Philox stream is below floor(p 2^32) (uint8 tensor)."""
+    dev = torch.device(device) if device is not None else (out.device if out is not None
+                                                          else torch.device("cuda", torch.cuda.current_device()))
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+    po = _dev_ptr(out, torch.uint8, "out", n, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_bernoulli(seed, stream_id, first, n, float(p), po, _stream(stream, dev)),
+               "ccl_bernoulli")
     return out
 
 

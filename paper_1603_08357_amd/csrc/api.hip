@@ -5,6 +5,8 @@
 #include <mutex>
 #include <vector>
 
+#include <math.h>
+
 #include "common.hpp"
 
 namespace ccl {
@@ -170,6 +172,36 @@ ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
   return launch_label_ell(n_sites, z_max, nn_list, z_max > 0 ? occupied : nullptr, labels_out,
                           (hipStream_t)stream, *d);
+}
+
+static ccl_status philox_common(uint64_t first, int64_t n, const void* out) {
+  if (n < 0 || (n > 0 && out == nullptr)) return CCL_ERR_INVALID_VALUE;
+  if (n > 0 && first > UINT64_MAX - (uint64_t)n) return CCL_ERR_INVALID_VALUE;
+  return CCL_OK;
+}
+
+ccl_status ccl_philox_u32(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n,
+                          uint32_t* out, void* stream) {
+  ccl_status st = philox_common(first, n, out);
+  if (st != CCL_OK || n == 0) return st;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_philox(seed, stream_id, first, n, 0, false, out, (hipStream_t)stream, *d);
+}
+
+ccl_status ccl_bernoulli(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n, double p,
+                         uint8_t* out, void* stream) {
+  ccl_status st = philox_common(first, n, out);
+  if (st != CCL_OK || n == 0) return st;
+  if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
+  // occupied iff word < floor(p 2^32); 2^32 (p >= 1) occupies every bond
+  const uint64_t threshold =
+      !(p > 0.0) ? 0 : (p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0));
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_philox(seed, stream_id, first, n, threshold, true, out, (hipStream_t)stream, *d);
 }
 
 size_t ccl_cluster_ids_workspace_size(int64_t n_sites) {

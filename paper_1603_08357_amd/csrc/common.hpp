@@ -98,6 +98,9 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
 size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds);
 ccl_status launch_label_ell(int64_t n, int32_t z, const int32_t* nn, const uint8_t* occ,
                             int32_t* label, hipStream_t s, const DeviceInfo& d);
+ccl_status launch_philox(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n,
+                         uint64_t threshold, bool bytes, void* out, hipStream_t s,
+                         const DeviceInfo& d);
 size_t cluster_ids_workspace_bytes(int64_t n);
 ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int32_t* n_clusters,
                               void* workspace, hipStream_t s, const DeviceInfo& d);

@@ -1,0 +1,74 @@
+// Bond occupancy drawn on the device: Philox4x32-10, the counter-based
+// generator of Salmon, Moraes, Dror and Shaw (SC'11), written here from its
+// published definition (ten rounds of two 32x32->64-bit products, the key
+// bumped by the Weyl constants between rounds).  Word j of block b of stream
+// s under seed K is output word j of Philox4x32-10 with counter
+// (b mod 2^32, b div 2^32, s, 0) and key (K mod 2^32, K div 2^32); word w of
+// the stream is word w mod 4 of block w div 4.  A bond with word u is
+// occupied when u < floor(p 2^32) (p >= 1: always).  This replaces the
+// paper's cuRAND draws (section 4) so that a Monte-Carlo loop never moves a
+// mask across PCIe.
+#include "common.hpp"
+
+namespace ccl {
+
+constexpr int kRngBlock = 256;
+
+// Philox4x32-10 round constants (the multipliers and Weyl increments of the
+// SC'11 paper).
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
+constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi_a = __umulhi(kPhiloxMulA, c.x), lo_a = kPhiloxMulA * c.x;
+    const uint32_t hi_b = __umulhi(kPhiloxMulB, c.z), lo_b = kPhiloxMulB * c.z;
+    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+    k0 += kPhiloxWeylA;
+    k1 += kPhiloxWeylB;
+  }
+  return c;
+}
+
+// One Philox block per lane: the words of block b that fall in
+// [first, first + n) are written (as words, or as occupancy bytes).
+template <bool BYTES>
+__global__ void __launch_bounds__(kRngBlock)
+    k_philox(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n, uint64_t threshold,
+             void* __restrict__ out) {
+  const uint64_t b0 = first >> 2, b1 = (first + (uint64_t)n - 1) >> 2;
+  const uint64_t stride = (uint64_t)gridDim.x * kRngBlock;
+  for (uint64_t b = b0 + (uint64_t)blockIdx.x * kRngBlock + threadIdx.x; b <= b1; b += stride) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)(b >> 32), stream_id, 0u),
+                                  (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint32_t word[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t idx = (b << 2) + (uint64_t)j;
+      if (idx < first || idx >= first + (uint64_t)n) continue;
+      if (BYTES)
+        static_cast<uint8_t*>(out)[idx - first] = (uint64_t)word[j] < threshold ? 1 : 0;
+      else
+        static_cast<uint32_t*>(out)[idx - first] = word[j];
+    }
+  }
+}
+
+ccl_status launch_philox(uint64_t seed, uint32_t stream_id, uint64_t first, int64_t n,
+                         uint64_t threshold, bool bytes, void* out, hipStream_t s,
+                         const DeviceInfo& d) {
+  const int64_t blocks = (int64_t)(((first + (uint64_t)n - 1) >> 2) - (first >> 2)) + 1;
+  const unsigned g = grid_for(blocks, kRngBlock, 8, d);
+  if (bytes)
+    CCL_LAUNCH("ccl_bernoulli", k_philox<true>, g, kRngBlock, 0, s, seed, stream_id, first, n,
+               threshold, out);
+  else
+    CCL_LAUNCH("ccl_philox_u32", k_philox<false>, g, kRngBlock, 0, s, seed, stream_id, first, n,
+               threshold, out);
+  return CCL_OK;
+}
+
+}  // namespace ccl

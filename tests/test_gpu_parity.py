@@ -185,6 +185,35 @@ def test_csr_almost_affine(ccl):
     np.testing.assert_array_equal(gpu_csr(ccl, rp, c, None), oracle.label_csr(n, rp, c, None))
 
 
+# ------------------------------------------------- occupancy on the device
+
+def test_device_philox_matches_the_host_generator(ccl):
+    """The device's Philox4x32-10 against the published known-answer vector
+    whose counter fits the stream layout (all zeros), then word for word and
+    bit for bit against the host generator (itself pinned to all the
+    published vectors) for unaligned ranges, several streams and seeds."""
+    row = read_golden("philox4x32_10_kat.txt")[0]
+    assert row[:6] == ["00000000"] * 6
+    want = [int(x, 16) for x in row[6:10]]
+    got = ccl.philox_u32(0, 0, 4).cpu().numpy().view(np.uint32).tolist()
+    assert got == want
+    for seed, stream, first, n in ((0, 0, 0, 4096), (gen.mix_seed(7, 3), 3, 5, 1001),
+                                   (2**64 - 1, 2**32 - 1, 2**40 + 3, 777)):
+        _say(f"philox seed={seed} stream={stream} first={first} n={n}")
+        got = ccl.philox_u32(seed, stream, n, first=first).cpu().numpy().view(np.uint32)
+        np.testing.assert_array_equal(got, gen.u32(seed, stream, n, first))
+    for p in (0.0, 1.0, 0.3473, 0.6527, 1e-9):
+        for first, n in ((0, 100_003), (7, 4099)):
+            got = ccl.bernoulli(11, gen.STREAM_OCC, n, p, first=first).cpu().numpy()
+            np.testing.assert_array_equal(got, gen.bernoulli(11, n, p, first=first))
+    # the headline workload's mask, drawn on the device, labels identically
+    g = gen.triangle_csr_realization(700, 0.3473, 2)
+    occ_dev = ccl.bernoulli(2, gen.STREAM_OCC, len(g.col), 0.3473)
+    np.testing.assert_array_equal(occ_dev.cpu().numpy(), g.occ)
+    lab = ccl.label_csr(dev(g.row_ptr), dev(g.col), occ_dev)
+    np.testing.assert_array_equal(lab.cpu().numpy(), oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ))
+
+
 # ------------------------------------------------------- cluster statistics
 
 def _gpu_stats(ccl, lab_t, top, bot):
