@@ -86,7 +86,7 @@ __device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, i
 // every lockstep join is full; `staged` (wavefront-uniform) carries the rest
 // to the next group.  The stack is private to the wavefront, whose LDS
 // accesses complete in order.
-constexpr int kJoinPer = 1;  // one join per lane: with the masked-or link, more only add latency
+constexpr int kJoinPer = 1;  // joins per lane per batch (one measured fastest with the masked-or link)
 constexpr int kJoinBatch = 64 * kJoinPer;
 constexpr int kStageCap = kJoinBatch - 1 + 256;  // leftover + one group of 64 x 4
 
