@@ -483,6 +483,58 @@ def test_batched_graph_replay(ccl, schedule):
         assert plan.check() == 0
 
 
+def test_monte_carlo_graph_replay(ccl):
+    """One Monte-Carlo realization -- occupancy drawn on the device, CSR
+    labeling, sequential ids, sizes, spanning test -- captured in a HIP graph
+    and replayed with eager work and synchronizations in between; every
+    replay must give the eager results, which equal the oracle's."""
+    L, p, seed = 300, 0.3473, 13
+    row_ptr, col = gen.triangle_csr(L)
+    n, m = L * L, len(col)
+    rp, dc = dev(row_ptr), dev(col)
+    occ = torch.empty(m, dtype=torch.uint8, device="cuda")
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
+    top = dev(np.arange(L, dtype=np.int32))
+    bot = dev(np.arange(n - L, n, dtype=np.int32))
+    s = torch.cuda.Stream()
+
+    def realization():
+        ccl.bernoulli(seed, gen.STREAM_OCC, m, p, out=occ, stream=s)
+        ccl.label_csr(rp, dc, occ, out=lab, workspace=ws, stream=s)
+        ids, count = ccl.cluster_ids(lab, stream=s)
+        sizes = ccl.cluster_sizes(lab, stream=s)
+        sp = ccl.spans(lab, top, bot, stream=s)
+        return ids, count, sizes, sp
+
+    host_occ = gen.bernoulli(seed, m, p)
+    want_lab = oracle.label_csr(n, row_ptr, col, host_occ)
+    want_ids, want_count = oracle.cluster_ids(want_lab)
+    with torch.cuda.stream(s):
+        eager = realization()
+    torch.cuda.synchronize()
+    eager = [t.cpu().numpy() for t in eager]
+    np.testing.assert_array_equal(lab.cpu().numpy(), want_lab)
+    np.testing.assert_array_equal(eager[0], want_ids)
+    assert int(eager[1][0]) == want_count
+    np.testing.assert_array_equal(eager[2], oracle.sizes_by_minimum(want_lab))
+    g = torch.cuda.CUDAGraph()
+    _say("monte-carlo graph capture")
+    with torch.cuda.graph(g, stream=s):
+        captured = realization()
+    for r in range(3):
+        lab.fill_(-7)
+        occ.fill_(9)
+        for t in captured:
+            t.fill_(-5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(lab.cpu().numpy(), want_lab, err_msg=f"replay {r}")
+        for got, ref in zip(captured, eager):
+            np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=f"replay {r}")
+
+
 # ------------------------------------------------------------ checks & errors
 
 def test_validate(ccl):
