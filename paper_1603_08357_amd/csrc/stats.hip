@@ -14,6 +14,7 @@ namespace ccl {
 constexpr int kIdBlock = 1024;
 constexpr int kIdPer = 4;                        // sites per lane
 constexpr int kIdSpan = kIdBlock * kIdPer;       // sites per workgroup
+static_assert(kIdPer == 4, "a lane moves its four sites as one int4");
 
 // Inclusive prefix sum of v over the 64 lanes of a wavefront.
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
@@ -49,25 +50,37 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* sc
 
 // ids[i] = number of cluster minima before i within the workgroup's span;
 // the span's count goes to part[block].
+// vec: label and ids are 16-byte aligned.
 __global__ void __launch_bounds__(kIdBlock)
     k_ids_local(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ ids,
-                int32_t* __restrict__ part) {
+                int32_t* __restrict__ part, bool vec) {
   __shared__ uint32_t scratch[kIdBlock / 64 + 1];
   const int64_t base = (int64_t)blockIdx.x * kIdSpan + (int64_t)threadIdx.x * kIdPer;
+  const bool whole = vec && base + kIdPer <= n;  // four sites in one 16-byte access
+  int32_t lab[kIdPer];
+  if (whole) {
+    const int4 v = reinterpret_cast<const int4*>(label + base)[0];
+    lab[0] = v.x; lab[1] = v.y; lab[2] = v.z; lab[3] = v.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kIdPer; ++k) lab[k] = base + k < n ? label[base + k] : -1;
+  }
   uint32_t f[kIdPer], s = 0;
 #pragma unroll
   for (int k = 0; k < kIdPer; ++k) {
-    const int64_t i = base + k;
-    f[k] = (i < n && label[i] == (int32_t)i) ? 1u : 0u;
+    f[k] = lab[k] == (int32_t)(base + k) ? 1u : 0u;
     s += f[k];
   }
   uint32_t total;
-  uint32_t run = block_exclusive_sum(s, scratch, &total);
+  const uint32_t run = block_exclusive_sum(s, scratch, &total);
+  const int32_t r0 = (int32_t)run, r1 = r0 + (int32_t)f[0], r2 = r1 + (int32_t)f[1], r3 = r2 + (int32_t)f[2];
+  if (whole) {
+    reinterpret_cast<int4*>(ids + base)[0] = make_int4(r0, r1, r2, r3);
+  } else {
+    const int32_t r[kIdPer] = {r0, r1, r2, r3};
 #pragma unroll
-  for (int k = 0; k < kIdPer; ++k) {
-    const int64_t i = base + k;
-    if (i < n) ids[i] = (int32_t)run;
-    run += f[k];
+    for (int k = 0; k < kIdPer; ++k)
+      if (base + k < n) ids[base + k] = r[k];
   }
   if (threadIdx.x == 0) part[blockIdx.x] = (int32_t)total;
 }
@@ -91,9 +104,15 @@ __global__ void __launch_bounds__(kIdBlock)
 
 // Adds each span's offset: ids[i] becomes the number of minima before i.
 __global__ void __launch_bounds__(kIdBlock)
-    k_ids_offset(int64_t n, const int32_t* __restrict__ part, int32_t* __restrict__ ids) {
+    k_ids_offset(int64_t n, const int32_t* __restrict__ part, int32_t* __restrict__ ids, bool vec) {
   const int64_t base = (int64_t)blockIdx.x * kIdSpan + (int64_t)threadIdx.x * kIdPer;
   const int32_t off = part[blockIdx.x];
+  if (vec && base + kIdPer <= n) {
+    int4 v = reinterpret_cast<int4*>(ids + base)[0];
+    v.x += off; v.y += off; v.z += off; v.w += off;
+    reinterpret_cast<int4*>(ids + base)[0] = v;
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < kIdPer; ++k)
     if (base + k < n) ids[base + k] += off;
@@ -117,9 +136,10 @@ ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int
                               void* workspace, hipStream_t s, const DeviceInfo& d) {
   const int64_t parts = (n + kIdSpan - 1) / kIdSpan;
   int32_t* part = static_cast<int32_t*>(workspace);
-  CCL_LAUNCH("ccl_ids_local", k_ids_local, (unsigned)parts, kIdBlock, 0, s, n, label, ids, part);
+  const bool vec = ((reinterpret_cast<uintptr_t>(label) | reinterpret_cast<uintptr_t>(ids)) & 15) == 0;
+  CCL_LAUNCH("ccl_ids_local", k_ids_local, (unsigned)parts, kIdBlock, 0, s, n, label, ids, part, vec);
   CCL_LAUNCH("ccl_ids_parts", k_ids_parts, 1u, kIdBlock, 0, s, parts, part, n_clusters);
-  CCL_LAUNCH("ccl_ids_offset", k_ids_offset, (unsigned)parts, kIdBlock, 0, s, n, part, ids);
+  CCL_LAUNCH("ccl_ids_offset", k_ids_offset, (unsigned)parts, kIdBlock, 0, s, n, part, ids, vec);
   CCL_LAUNCH("ccl_ids_gather", k_ids_gather, grid_for(n, kIdBlock, 8, d), kIdBlock, 0, s, n, label,
              ids);
   return CCL_OK;
