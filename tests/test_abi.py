@@ -111,3 +111,42 @@ def test_validation_argument_errors(lib):
     assert lib.ccl_validate_edges(5, 0, None, None, ctypes.byref(bad), None) == 0
     assert bad.value == 0
     assert lib.ccl_validate_csr(5, None, None, 0, ctypes.byref(bad), None) == INVALID
+
+
+def test_more_host_side_argument_errors(lib):
+    """The neighbour-list path, the statistics and the device generator
+    reject bad arguments on the host."""
+    INVALID = 1
+    P = ctypes.c_void_p
+    # ccl_label_ell: negative sizes, missing pointers, oversized list, aliasing
+    assert lib.ccl_label_ell(-1, 3, P(64), None, P(4096), None) == INVALID
+    assert lib.ccl_label_ell(10, -1, P(64), None, P(4096), None) == INVALID
+    assert lib.ccl_label_ell(10, 3, None, None, P(4096), None) == INVALID
+    assert lib.ccl_label_ell(10, 3, P(64), None, None, None) == INVALID
+    assert lib.ccl_label_ell(1 << 30, 1 << 11, P(64), None, P(1 << 40), None) == INVALID
+    assert lib.ccl_label_ell(10, 3, P(4096), None, P(4096 + 8), None) == INVALID
+    assert lib.ccl_label_ell(0, 3, None, None, None, None) == 0
+    # ccl_cluster_ids: workspace size and alignment, aliasing
+    n = 10_000
+    need = lib.ccl_cluster_ids_workspace_size(n)
+    assert need == 4 * ((n + 4095) // 4096) and lib.ccl_cluster_ids_workspace_size(0) == 0
+    lab, ids, cnt, ws = P(1 << 20), P(1 << 24), P(1 << 28), P(1 << 32)
+    assert lib.ccl_cluster_ids(n, lab, ids, cnt, ws, need - 4, None) == INVALID
+    assert lib.ccl_cluster_ids(n, lab, ids, cnt, P((1 << 32) + 2), need, None) == INVALID
+    assert lib.ccl_cluster_ids(n, lab, lab, cnt, ws, need, None) == INVALID
+    assert lib.ccl_cluster_ids(n, lab, ids, None, ws, need, None) == INVALID
+    assert lib.ccl_cluster_ids(-1, lab, ids, cnt, ws, need, None) == INVALID
+    # ccl_cluster_sizes / ccl_spans
+    assert lib.ccl_cluster_sizes(n, lab, lab, None) == INVALID
+    assert lib.ccl_cluster_sizes(n, None, ids, None) == INVALID
+    assert lib.ccl_spans(n, lab, 4, None, 4, P(64), P(1 << 36), P(1 << 38), None) == INVALID
+    assert lib.ccl_spans(n, lab, -1, P(64), 4, P(64), P(1 << 36), P(1 << 38), None) == INVALID
+    assert lib.ccl_spans(n, lab, 4, P(64), 4, P(64), P(1 << 36), None, None) == INVALID
+    assert lib.ccl_spans(0, None, 1, P(64), 1, P(64), None, P(1 << 38), None) == INVALID
+    # device generator: size overflow, missing output, NaN probability
+    assert lib.ccl_philox_u32(1, 0, 2**64 - 2, 10, P(64), None) == INVALID
+    assert lib.ccl_philox_u32(1, 0, 0, 10, None, None) == INVALID
+    assert lib.ccl_philox_u32(1, 0, 0, -1, P(64), None) == INVALID
+    assert lib.ccl_philox_u32(1, 0, 0, 0, None, None) == 0
+    assert lib.ccl_bernoulli(1, 0, 0, 10, float("nan"), P(64), None) == INVALID
+    assert lib.ccl_bernoulli(1, 0, 0, 10, 0.5, None, None) == INVALID
