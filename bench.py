@@ -378,7 +378,8 @@ def bench_monte_carlo(L, p, seed, steps, warmup):
     """Realizations per second of the headline workload with each
     realization's occupancy drawn on the device (ccl_bernoulli, the same
     Philox stream the host generator uses) before it is labelled: nothing
-    crosses PCIe inside the loop."""
+    crosses PCIe inside the loop.  `fused_draw`: the same realizations with
+    the draw inside the tile kernel (ccl_label_csr_philox), no mask at all."""
     import numpy as np
     import torch
     import gen
@@ -397,15 +398,31 @@ def bench_monte_carlo(L, p, seed, steps, warmup):
         ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream)
         k[0] += 1
 
+    def fused():
+        ccl.label_csr_philox(rp, dc, gen.mix_seed(seed, k[0]), gen.STREAM_OCC, p, out=out,
+                             workspace=ws, stream=stream)
+        k[0] += 1
+
     ms, _ = time_steps(one, steps, warmup, stream)
     kern = traced_kernels(one, steps)
+    ms_f, _ = time_steps(fused, steps, warmup, stream)
+    kern_f = traced_kernels(fused, steps)
     # the device draws what the host generator draws (a prefix, bit for bit)
     ccl.bernoulli(gen.mix_seed(seed, 0), gen.STREAM_OCC, m, p, out=occ, stream=stream)
     head = occ[: 1 << 22].cpu().numpy()
     same = bool(np.array_equal(head, gen.bernoulli(gen.mix_seed(seed, 0), 1 << 22, p)))
+    # and the draw inside the tile kernel labels as the drawn mask does
+    ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream)
+    sep = out.clone()
+    ccl.label_csr_philox(rp, dc, gen.mix_seed(seed, 0), gen.STREAM_OCC, p, out=out, workspace=ws,
+                         stream=stream)
     return {"ms_per_realization": round(ms, 5), "realizations_per_s": round(1e3 / ms, 1),
             "kernels": {k_: round(v["mean_ms"], 5) for k_, v in kern.items()},
-            "device_mask_equals_host_generator": same}
+            "device_mask_equals_host_generator": same,
+            "fused_draw": {"ms_per_realization": round(ms_f, 5),
+                           "realizations_per_s": round(1e3 / ms_f, 1),
+                           "kernels": {k_: round(v["mean_ms"], 5) for k_, v in kern_f.items()},
+                           "labels_equal_mask_path": bool(torch.equal(sep, out))}}
 
 
 def bench_rspan_full(samples):

@@ -121,6 +121,21 @@ ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_pt
                          const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * ccl_label_csr with the occupancy drawn inside the tile kernel instead of
+ * read from a mask: bond e (the entry col[e]) is occupied when word e of the
+ * Philox4x32-10 stream (seed, stream_id) lies below floor(p 2^32), exactly
+ * the mask ccl_bernoulli(seed, stream_id, 0, row_ptr[N], p, ...) writes.
+ * This is the Monte-Carlo setting of section 4 (a new random configuration
+ * per sample) without a mask in memory: the draw costs arithmetic, not HBM
+ * traffic.  p is NaN: CCL_ERR_INVALID_VALUE; p <= 0: no bond occupied;
+ * p >= 1: every bond.  The other arguments and errors are ccl_label_csr's.
+ */
+ccl_status ccl_label_csr_philox(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                                const int32_t* col, uint64_t seed, uint32_t stream_id, double p,
+                                int32_t* labels_out, void* workspace, size_t workspace_bytes,
+                                void* stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /*

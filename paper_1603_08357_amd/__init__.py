@@ -17,7 +17,8 @@ import numpy as np
 import torch  # first: the library then binds to the HIP runtime torch loaded
 
 __all__ = [
-    "CclError", "label", "label_csr", "csr_workspace_bytes", "Plan", "Tuning",
+    "CclError", "label", "label_csr", "label_csr_philox", "label_ell", "csr_workspace_bytes",
+    "philox_u32", "bernoulli", "cluster_ids", "cluster_sizes", "spans", "Plan", "Tuning",
     "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
     "library_path", "version",
 ]
@@ -60,6 +61,8 @@ def _load():
         "ccl_label": (st, [i64, i64, P, P, P, P, P]),
         "ccl_label_csr_workspace_size": (sz, [i64, i64]),
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
+        "ccl_label_csr_philox": (st, [i64, i64, P, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
+                                      P, P, sz, P]),
         "ccl_label_ell": (st, [i64, i32, P, P, P, P]),
         "ccl_philox_u32": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, P, P]),
         "ccl_bernoulli": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, ctypes.c_double,
@@ -246,13 +249,7 @@ def csr_workspace_bytes(n_sites: int, n_bonds: int) -> int:
     return int(_lib.ccl_label_csr_workspace_size(n_sites, n_bonds))
 
 
-def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None = None,
-              out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-              stream=None) -> torch.Tensor:
-    """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1,
-    bonds row_ptr[0] .. row_ptr[n]-1 of col (len(col) bounds their count).
-    `workspace` (uint8, >= csr_workspace_bytes(n, len(col)) bytes) is
-    allocated when None."""
+def _csr_args(row_ptr, col, out, workspace):
     dev = row_ptr.device
     n = row_ptr.numel() - 1
     if n < 0:
@@ -260,7 +257,6 @@ def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None
     m = col.numel()
     prp = _dev_ptr(row_ptr, torch.int32, "row_ptr", None, dev)
     pc = _dev_ptr(col, torch.int32, "col", None, dev)
-    po = _dev_ptr(occ, torch.uint8, "occ", m, dev)
     if out is None:
         out = torch.empty(n, dtype=torch.int32, device=dev)
     pl = _dev_ptr(out, torch.int32, "out", n, dev)
@@ -269,9 +265,34 @@ def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     pw = _dev_ptr(workspace, torch.uint8, "workspace", None, dev)
     wbytes = workspace.numel() if workspace is not None else 0
+    return dev, n, m, prp, pc, out, pl, pw, wbytes
+
+
+def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None = None,
+              out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1,
+    bonds row_ptr[0] .. row_ptr[n]-1 of col (len(col) bounds their count).
+    `workspace` (uint8, >= csr_workspace_bytes(n, len(col)) bytes) is
+    allocated when None."""
+    dev, n, m, prp, pc, out, pl, pw, wbytes = _csr_args(row_ptr, col, out, workspace)
+    po = _dev_ptr(occ, torch.uint8, "occ", m, dev)
     with torch.cuda.device(dev):
         _check(_lib.ccl_label_csr(n, m, prp, pc, po, pl, pw, wbytes, _stream(stream, dev)),
                "ccl_label_csr")
+    return out
+
+
+def label_csr_philox(row_ptr: torch.Tensor, col: torch.Tensor, seed: int, stream_id: int, p: float,
+                     out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """label_csr with bond e occupied when word e of the Philox stream
+    (seed, stream_id) is below floor(p 2^32), drawn inside the kernel: the
+    labels of label_csr(row_ptr, col, bernoulli(seed, stream_id, len(col), p))."""
+    dev, n, m, prp, pc, out, pl, pw, wbytes = _csr_args(row_ptr, col, out, workspace)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label_csr_philox(n, m, prp, pc, seed, stream_id, float(p), pl, pw, wbytes,
+                                         _stream(stream, dev)), "ccl_label_csr_philox")
     return out
 
 

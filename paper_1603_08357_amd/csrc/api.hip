@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include "common.hpp"
+#include "philox.hpp"
 
 namespace ccl {
 
@@ -133,9 +134,10 @@ size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds) {
   return csr_workspace_bytes(n_sites, n_bonds);
 }
 
-ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
-                         const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
-                         void* workspace, size_t workspace_bytes, void* stream) {
+static ccl_status label_csr_checked(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                                    const int32_t* col, const uint8_t* occupied,
+                                    const PhiloxOcc* draw, int32_t* labels_out, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
   if (n_sites < 0 || n_sites > INT32_MAX || n_bonds < 0 || n_bonds > INT32_MAX)
     return CCL_ERR_INVALID_VALUE;
   if (n_sites == 0) return CCL_OK;
@@ -152,8 +154,30 @@ ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_pt
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
-  return launch_label_csr(n_sites, row_ptr, col, occupied, labels_out, need ? workspace : nullptr,
-                          (hipStream_t)stream, *d);
+  return launch_label_csr(n_sites, row_ptr, col, occupied, draw, labels_out,
+                          need ? workspace : nullptr, (hipStream_t)stream, *d);
+}
+
+// occupied iff word < floor(p 2^32); 2^32 (p >= 1) occupies every bond
+static uint64_t occupancy_threshold(double p) {
+  return !(p > 0.0) ? 0 : (p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0));
+}
+
+ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                         const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+  return label_csr_checked(n_sites, n_bonds, row_ptr, col, occupied, nullptr, labels_out,
+                           workspace, workspace_bytes, stream);
+}
+
+ccl_status ccl_label_csr_philox(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
+                                const int32_t* col, uint64_t seed, uint32_t stream_id, double p,
+                                int32_t* labels_out, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
+  const PhiloxOcc draw{seed, stream_id, occupancy_threshold(p)};
+  return label_csr_checked(n_sites, n_bonds, row_ptr, col, nullptr, &draw, labels_out, workspace,
+                           workspace_bytes, stream);
 }
 
 ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
@@ -195,9 +219,7 @@ ccl_status ccl_bernoulli(uint64_t seed, uint32_t stream_id, uint64_t first, int6
   ccl_status st = philox_common(first, n, out);
   if (st != CCL_OK || n == 0) return st;
   if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
-  // occupied iff word < floor(p 2^32); 2^32 (p >= 1) occupies every bond
-  const uint64_t threshold =
-      !(p > 0.0) ? 0 : (p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0));
+  const uint64_t threshold = occupancy_threshold(p);
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;

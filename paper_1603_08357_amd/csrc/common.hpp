@@ -92,9 +92,12 @@ ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const Device
 ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                               const uint8_t* occ, int32_t* label, hipStream_t s,
                               const DeviceInfo& d);
+struct PhiloxOcc;
+// occ: a mask aligned with col, or NULL; draw (only with occ NULL): draw the
+// occupancy of bond e as word e of that Philox stream; both NULL: all occupied
 ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
-                            const uint8_t* occ, int32_t* label, void* workspace,
-                            hipStream_t s, const DeviceInfo& d);
+                            const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
+                            void* workspace, hipStream_t s, const DeviceInfo& d);
 size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds);
 ccl_status launch_label_ell(int64_t n, int32_t z, const int32_t* nn, const uint8_t* occ,
                             int32_t* label, hipStream_t s, const DeviceInfo& d);

@@ -18,6 +18,7 @@
 // larger than the site, so kernels 2-3 see a valid forest and finish the job
 // exactly as the single-pass method would.
 #include "common.hpp"
+#include "philox.hpp"
 #include "uf.hpp"
 
 namespace ccl {
@@ -159,11 +160,17 @@ __device__ __forceinline__ uint32_t reserve_slots(uint32_t mine, uint32_t* n_out
 // Buffer resources are based at the tile's first row and first bond, so
 // offsets stay small whatever the graph size; a tile with 2^30 or more bonds
 // uses plain loads.
-template <bool HAS_OCC>
+// Occupancy of the bonds: all occupied, read from a mask aligned with col, or
+// drawn from the Philox stream on the fly (bond e is word e of the stream;
+// the same draw ccl_bernoulli writes into a mask).
+constexpr int kOccAll = 0, kOccMask = 1, kOccDraw = 2;
+
+template <int OCC>
 __global__ void __launch_bounds__(kTileBlock)
     k_csr_tile(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
-               int2* __restrict__ pairs, int2* __restrict__ seg) {
+               int2* __restrict__ pairs, int2* __restrict__ seg, PhiloxOcc rng) {
+  constexpr bool HAS_OCC = OCC == kOccMask, DRAW = OCC == kOccDraw;
   __shared__ uint16_t par[kCsrTile];  // tile-relative parents, 16 bits each
   __shared__ uint32_t stage[kTileBlock / 64][kStageCap];  // per-wavefront join staging
   __shared__ uint32_t n_out;
@@ -198,7 +205,8 @@ __global__ void __launch_bounds__(kTileBlock)
     const int32_t q = (G * k + u) * kTileBlock + tid;
     const uint32_t off = q < full ? 4u * (uint32_t)q : kOffNone;
     cv = buf_i32x4(rc, off * 4u);
-    ov = HAS_OCC ? buf_u32(ro, off) : (off != kOffNone ? 0x01010101u : 0u);
+    ov = HAS_OCC ? buf_u32(ro, off)
+                 : (off == kOffNone ? 0u : (DRAW ? philox_occ4(rng, (uint64_t)e_begin + off) : 0x01010101u));
   };
   if (affine_try) {
 #pragma unroll
@@ -293,7 +301,7 @@ __global__ void __launch_bounds__(kTileBlock)
     if (tid == 0 && full * 4 < nb) {
       for (int32_t x = 4 * full; x < nb; ++x) {
         const int64_t ge = (int64_t)e_begin + x;
-        if (HAS_OCC && occ[ge] == 0) continue;
+        if ((HAS_OCC && occ[ge] == 0) || (DRAW && !philox_occupied(rng, (uint64_t)ge))) continue;
         const int32_t v = col[ge];
         if (tile_bond(par, affine_row(x, magic), v, lo, cnt)) {
           const uint32_t sl =
@@ -322,7 +330,10 @@ __global__ void __launch_bounds__(kTileBlock)
           const uint32_t off =
               (fast && e < rb[k] && base + k * kTileBlock + tid < cnt) ? (uint32_t)e : kOffNone;
           cv[k][j] = buf_i32(rc, off * 4u);
-          ov[k][j] = HAS_OCC ? buf_u8(ro, off) : (off != kOffNone ? 1u : 0u);
+          ov[k][j] = HAS_OCC ? buf_u8(ro, off)
+                             : (off == kOffNone ? 0u
+                                                : (DRAW ? (philox_occupied(rng, (uint64_t)e_begin + off) ? 1u : 0u)
+                                                        : 1u));
         }
       int32_t na[kRowsPerThread], nb[kRowsPerThread];
 #pragma unroll
@@ -363,7 +374,7 @@ __global__ void __launch_bounds__(kTileBlock)
         if (t >= cnt) continue;
         for (int32_t e = ra[k] + (fast ? kDegFast : 0); e < rb[k]; ++e) {
           const int64_t ge = (int64_t)e_begin + e;
-          if (HAS_OCC && occ[ge] == 0) continue;
+          if ((HAS_OCC && occ[ge] == 0) || (DRAW && !philox_occupied(rng, (uint64_t)ge))) continue;
           const int32_t v = col[ge];
           if (tile_bond(par, t, v, lo, cnt)) {
             const uint32_t sl =
@@ -655,8 +666,8 @@ size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds) {
 }
 
 ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
-                            const uint8_t* occ, int32_t* label, void* workspace,
-                            hipStream_t s, const DeviceInfo& d) {
+                            const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
+                            void* workspace, hipStream_t s, const DeviceInfo& d) {
   if (n == 0) return CCL_OK;
   const int64_t n_tiles = (n + kCsrTile - 1) / kCsrTile;
   int2* seg = nullptr;
@@ -666,12 +677,16 @@ ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* co
     pairs = reinterpret_cast<int2*>(static_cast<char*>(workspace) +
                                     (((size_t)n_tiles * sizeof(int2) + 255) & ~(size_t)255));
   }
+  const PhiloxOcc rng = draw != nullptr ? *draw : PhiloxOcc{0, 0, 0};
   if (occ != nullptr)
-    CCL_LAUNCH("ccl_csr_tile", k_csr_tile<true>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
-               col, occ, label, pairs, seg);
+    CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccMask>, (unsigned)n_tiles, kTileBlock, 0, s, n,
+               row_ptr, col, occ, label, pairs, seg, rng);
+  else if (draw != nullptr)
+    CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccDraw>, (unsigned)n_tiles, kTileBlock, 0, s, n,
+               row_ptr, col, occ, label, pairs, seg, rng);
   else
-    CCL_LAUNCH("ccl_csr_tile", k_csr_tile<false>, (unsigned)n_tiles, kTileBlock, 0, s, n, row_ptr,
-               col, occ, label, pairs, seg);
+    CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccAll>, (unsigned)n_tiles, kTileBlock, 0, s, n,
+               row_ptr, col, occ, label, pairs, seg, rng);
   if (n_tiles == 1) return CCL_OK;
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)(n_tiles * kCrossSplit), kCrossBlock, 0, s, pairs, seg,
              label);

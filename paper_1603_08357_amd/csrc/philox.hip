@@ -9,29 +9,11 @@
 // paper's cuRAND draws (section 4) so that a Monte-Carlo loop never moves a
 // mask across PCIe.
 #include "common.hpp"
+#include "philox.hpp"
 
 namespace ccl {
 
 constexpr int kRngBlock = 256;
-
-// Philox4x32-10 round constants (the multipliers and Weyl increments of the
-// SC'11 paper).
-constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
-constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
-constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
-constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
-
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    const uint32_t hi_a = __umulhi(kPhiloxMulA, c.x), lo_a = kPhiloxMulA * c.x;
-    const uint32_t hi_b = __umulhi(kPhiloxMulB, c.z), lo_b = kPhiloxMulB * c.z;
-    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
-    k0 += kPhiloxWeylA;
-    k1 += kPhiloxWeylB;
-  }
-  return c;
-}
 
 // One Philox block per lane: the words of block b that fall in
 // [first, first + n) are written (as words, or as occupancy bytes).
@@ -42,8 +24,7 @@ __global__ void __launch_bounds__(kRngBlock)
   const uint64_t b0 = first >> 2, b1 = (first + (uint64_t)n - 1) >> 2;
   const uint64_t stride = (uint64_t)gridDim.x * kRngBlock;
   for (uint64_t b = b0 + (uint64_t)blockIdx.x * kRngBlock + threadIdx.x; b <= b1; b += stride) {
-    const uint4 w = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)(b >> 32), stream_id, 0u),
-                                  (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint4 w = philox_block(seed, stream_id, b);
     const uint32_t word[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

@@ -150,3 +150,11 @@ def test_more_host_side_argument_errors(lib):
     assert lib.ccl_philox_u32(1, 0, 0, 0, None, None) == 0
     assert lib.ccl_bernoulli(1, 0, 0, 10, float("nan"), P(64), None) == INVALID
     assert lib.ccl_bernoulli(1, 0, 0, 10, 0.5, None, None) == INVALID
+    # ccl_label_csr_philox: NaN probability, then ccl_label_csr's own checks
+    rp, col, lab = P(1 << 20), P(1 << 24), P(1 << 28)
+    assert lib.ccl_label_csr_philox(10, 30, rp, col, 1, 0, float("nan"), lab, None, 0, None) == INVALID
+    assert lib.ccl_label_csr_philox(-1, 30, rp, col, 1, 0, 0.5, lab, None, 0, None) == INVALID
+    assert lib.ccl_label_csr_philox(10, 30, None, col, 1, 0, 0.5, lab, None, 0, None) == INVALID
+    assert lib.ccl_label_csr_philox(10, 30, rp, col, 1, 0, 0.5, rp, None, 0, None) == INVALID
+    assert lib.ccl_label_csr_philox(1 << 20, 1 << 22, rp, col, 1, 0, 0.5, lab, None, 0, None) == INVALID
+    assert lib.ccl_label_csr_philox(0, 0, None, None, 1, 0, 0.5, None, None, 0, None) == 0

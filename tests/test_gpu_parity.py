@@ -214,6 +214,46 @@ def test_device_philox_matches_the_host_generator(ccl):
     np.testing.assert_array_equal(lab.cpu().numpy(), oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ))
 
 
+def _fused(ccl, rp, c, seed, p):
+    _say(f"ccl_label_csr_philox n={len(rp) - 1} m={len(c)} e0={int(rp[0])} seed={seed} p={p}")
+    out = ccl.label_csr_philox(dev(rp), dev(c), seed, gen.STREAM_OCC, p)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_csr_with_drawn_occupancy(ccl):
+    """The tile kernel drawing bond e's occupancy as word e of the Philox
+    stream labels exactly as the host-drawn mask does: the affine path over
+    several tiles and a ragged last tile, tiles whose first bond is not a
+    multiple of four (row_ptr[0] = 1..3, so the four-bond draws straddle two
+    Philox blocks), the row path (ragged degrees, rows longer than the ones
+    kept in registers) and the limits p = 0, p = 1."""
+    g = gen.triangle_csr_realization(700, 0.3473, 2)
+    for p in (0.3473, 0.0, 1.0, 1e-9):
+        occ = gen.bernoulli(2, len(g.col), p)
+        np.testing.assert_array_equal(_fused(ccl, g.row_ptr, g.col, 2, p),
+                                      oracle.label_csr(g.n_sites, g.row_ptr, g.col, occ))
+    rp0, c0 = gen.triangle_csr(300)
+    for e0 in (1, 2, 3):
+        rp = (rp0 + e0).astype(np.int32)
+        c = np.concatenate([np.full(e0, 7, np.int32), c0]).astype(np.int32)
+        occ = gen.bernoulli(5, len(c), 0.3473)
+        np.testing.assert_array_equal(_fused(ccl, rp, c, 5, 0.3473),
+                                      oracle.label_csr(len(rp) - 1, rp, c, occ))
+    rng = np.random.default_rng(31)
+    n = 150_001
+    deg = rng.integers(0, 13, n)
+    deg[::997] = 40
+    rp = np.concatenate([[3], 3 + np.cumsum(deg)]).astype(np.int32)
+    c = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    for p in (0.2, 0.05):
+        occ = gen.bernoulli(9, len(c), p)
+        np.testing.assert_array_equal(_fused(ccl, rp, c, 9, p), oracle.label_csr(n, rp, c, occ))
+    with pytest.raises(ccl.CclError) as e:
+        ccl.label_csr_philox(dev(g.row_ptr), dev(g.col), 2, gen.STREAM_OCC, float("nan"))
+    assert e.value.status == 1
+
+
 # ------------------------------------------------------- cluster statistics
 
 def _gpu_stats(ccl, lab_t, top, bot):
