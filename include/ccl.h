@@ -240,7 +240,8 @@ ccl_status ccl_bernoulli(uint64_t seed, uint32_t stream_id, uint64_t first, int6
 /*
  * These take a finished labeling (labels[i] = minimum site id of i's
  * cluster, as every ccl_label* call returns); on anything else the results
- * are undefined.  Asynchronous on `stream`; off the labeling path.  They
+ * are undefined, but no access leaves the buffers (labels outside [0, N) are
+ * skipped).  Asynchronous on `stream`; off the labeling path.  They
  * serve the percolation application of section 4.
  */
 
@@ -273,7 +274,8 @@ ccl_status ccl_cluster_sizes(int64_t n_sites, const int32_t* labels, int32_t* si
  * The spanning test of section 4: *result_out = 1 when one cluster holds a
  * site of sites_a and a site of sites_b (e.g. the first and the last row of a
  * lattice), else 0.
- *   sites_a, sites_b  device int32[n_a], int32[n_b], ids in [0, N)
+ *   sites_a, sites_b  device int32[n_a], int32[n_b], ids in [0, N) (others
+ *                     are skipped)
  *   flags             device uint8[N] workspace, contents need not be
  *                     initialised
  *   result_out        device int32

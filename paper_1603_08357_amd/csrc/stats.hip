@@ -120,11 +120,15 @@ __global__ void __launch_bounds__(kIdBlock)
 
 // ids[i] = ids[label[i]]: a minimum's entry is its own id and is rewritten
 // with the same value, and only minima are read, so this is done in place.
+// A label outside [0, n) (not a finished labeling) gives -1, never an access
+// outside the arrays.
 __global__ void __launch_bounds__(kIdBlock)
     k_ids_gather(int64_t n, const int32_t* __restrict__ label, int32_t* ids) {
   const int64_t stride = (int64_t)gridDim.x * kIdBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kIdBlock + threadIdx.x; i < n; i += stride)
-    ids[i] = ids[label[i]];
+  for (int64_t i = (int64_t)blockIdx.x * kIdBlock + threadIdx.x; i < n; i += stride) {
+    const int32_t r = label[i];
+    ids[i] = (r >= 0 && r < n) ? ids[r] : -1;
+  }
 }
 
 size_t cluster_ids_workspace_bytes(int64_t n) {
@@ -177,6 +181,7 @@ __global__ void __launch_bounds__(kSzBlock)
   int32_t cur = -1;
   uint32_t run = 0;
   auto add = [&](int32_t r, uint32_t c) {
+    if (r < 0 || r >= n) return;  // not a site id: skipped
     uint32_t h = ((uint32_t)r * 2654435761u) & (kSzSlots - 1);
     for (;;) {
       int32_t seen = -1;
@@ -218,7 +223,8 @@ ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes,
 // ---------------------------------------------------------------- spanning
 
 // flags[label[a]] = 1 for every site a of A; then any site b of B whose
-// cluster is flagged sets *result.  Flag stores are plain byte stores of the
+// cluster is flagged sets *result.  Site ids and labels outside [0, n) are
+// skipped.  Flag stores are plain byte stores of the
 // same value (races are benign); the flag array is cleared by a kernel, so
 // the sequence can be captured in a graph.
 constexpr int kSpBlock = 256;
@@ -231,20 +237,26 @@ __global__ void __launch_bounds__(kSpBlock)
 }
 
 __global__ void __launch_bounds__(kSpBlock)
-    k_span_mark(int64_t n_a, const int32_t* __restrict__ a, const int32_t* __restrict__ label,
+    k_span_mark(int64_t n, int64_t n_a, const int32_t* __restrict__ a, const int32_t* __restrict__ label,
                 uint8_t* __restrict__ flags) {
   const int64_t stride = (int64_t)gridDim.x * kSpBlock;
-  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_a; j += stride)
-    flags[label[a[j]]] = 1;
+  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_a; j += stride) {
+    const int32_t i = a[j];
+    const int32_t r = (i >= 0 && i < n) ? label[i] : -1;
+    if (r >= 0 && r < n) flags[r] = 1;
+  }
 }
 
 __global__ void __launch_bounds__(kSpBlock)
-    k_span_test(int64_t n_b, const int32_t* __restrict__ b, const int32_t* __restrict__ label,
+    k_span_test(int64_t n, int64_t n_b, const int32_t* __restrict__ b, const int32_t* __restrict__ label,
                 const uint8_t* __restrict__ flags, int32_t* __restrict__ result) {
   const int64_t stride = (int64_t)gridDim.x * kSpBlock;
   bool hit = false;
-  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_b; j += stride)
-    hit = hit || flags[label[b[j]]] != 0;
+  for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_b; j += stride) {
+    const int32_t i = b[j];
+    const int32_t r = (i >= 0 && i < n) ? label[i] : -1;
+    hit = hit || (r >= 0 && r < n && flags[r] != 0);
+  }
   if (__any(hit) && (threadIdx.x & 63) == 0) *result = 1;
 }
 
@@ -254,10 +266,10 @@ ccl_status launch_spans(int64_t n, const int32_t* label, int64_t n_a, const int3
   CCL_LAUNCH("ccl_span_clear", k_span_clear, grid_for(n, kSpBlock, 8, d), kSpBlock, 0, s, n, flags,
              result);
   if (n_a > 0 && n_b > 0) {
-    CCL_LAUNCH("ccl_span_mark", k_span_mark, grid_for(n_a, kSpBlock, 8, d), kSpBlock, 0, s, n_a, a,
-               label, flags);
-    CCL_LAUNCH("ccl_span_test", k_span_test, grid_for(n_b, kSpBlock, 8, d), kSpBlock, 0, s, n_b, b,
-               label, flags, result);
+    CCL_LAUNCH("ccl_span_mark", k_span_mark, grid_for(n_a, kSpBlock, 8, d), kSpBlock, 0, s, n, n_a,
+               a, label, flags);
+    CCL_LAUNCH("ccl_span_test", k_span_test, grid_for(n_b, kSpBlock, 8, d), kSpBlock, 0, s, n, n_b,
+               b, label, flags, result);
   }
   return CCL_OK;
 }

@@ -305,6 +305,18 @@ def test_cluster_statistics(ccl):
         assert sp
     e = torch.zeros(0, dtype=torch.int32, device="cuda")
     assert ccl.spans(dev(np.arange(10, dtype=np.int32)), e, dev(np.arange(3, dtype=np.int32))).item() == 0
+    # labels and site ids outside [0, N) are skipped: ids -1, no size, no flag
+    n = 9000
+    lab = np.arange(n, dtype=np.int32)
+    lab[[5, 4097, 8999]] = [n + 5, -3, 2**31 - 1]
+    valid = lab == np.arange(n)
+    ids, count, sizes, _ = _gpu_stats(ccl, dev(lab), np.zeros(1, np.int32), np.zeros(1, np.int32))
+    np.testing.assert_array_equal(ids, np.where(valid, np.cumsum(valid) - 1, -1))
+    assert count == int(valid.sum())
+    np.testing.assert_array_equal(sizes, valid.astype(np.int32))
+    a = dev(np.array([-1, n, 0, 5], np.int32))
+    assert ccl.spans(dev(lab), a, dev(np.array([n + 100, 0], np.int32))).item() == 1
+    assert ccl.spans(dev(lab), a, dev(np.array([n + 100, -7, 5], np.int32))).item() == 0
 
 
 # ------------------------------------------- the paper's neighbour-list path
