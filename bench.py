@@ -72,11 +72,18 @@ def path_bytes_edges(n: int, m: int) -> float:
 
 
 def kernel_source_hash() -> str:
+    """Hash of what the CSR path's kernels are built from (csr.hip, the
+    headers it includes, the build flags): counter figures taken on other
+    sources are not reported."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1603_08357_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+    pkg = os.path.join(ROOT, "paper_1603_08357_amd")
+    csrc = os.path.join(pkg, "csrc")
+    files = [os.path.join(csrc, "csr.hip")]
+    files += sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".hpp"))
+    files += [os.path.join(ROOT, "include", "ccl.h"), os.path.join(pkg, "build.py")]
+    for path in files:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -372,6 +379,12 @@ def bench_stats(lab_headline, steps, samples=32, L=512):
             curve[str(p)] = round(hits / samples, 4)
         res[f"R_span_{kind}_L{L}"] = {"n_sites": nn, "samples": samples, "R_span": curve}
     return res
+
+
+def bench_monte_carlo_set(L, seed, steps, warmup):
+    """bench_monte_carlo at the paper's three occupancies, 0.5, 1 and 1.5 p_c
+    (section 4's timing runs); the p_c entry also checks the device draws."""
+    return {f"p{p}": bench_monte_carlo(L, p, seed, steps, warmup) for p in (0.3473, 0.1736, 0.5209)}
 
 
 def bench_monte_carlo(L, p, seed, steps, warmup):
@@ -791,7 +804,7 @@ def main():
         except Exception as e:
             extra["serving"] = f"failed: {type(e).__name__}: {e}"
         try:
-            extra["monte_carlo"] = bench_monte_carlo(args.L, args.p, args.seed, args.steps, args.warmup)
+            extra["monte_carlo"] = bench_monte_carlo_set(args.L, args.seed, args.steps, args.warmup)
         except Exception as e:
             extra["monte_carlo"] = f"failed: {type(e).__name__}: {e}"
         try:
