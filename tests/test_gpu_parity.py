@@ -587,6 +587,45 @@ def test_monte_carlo_graph_replay(ccl):
             np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=f"replay {r}")
 
 
+def test_drawn_occupancy_graph_replay(ccl):
+    """The realization with its occupancy drawn inside the tile kernel
+    (ccl_label_csr_philox) and its cluster sizes, captured in a HIP graph and
+    replayed with eager work in between: every replay gives the oracle's
+    labels for the host generator's mask."""
+    L, p, seed = 300, 0.3473, 17
+    row_ptr, col = gen.triangle_csr(L)
+    n, m = L * L, len(col)
+    rp, dc = dev(row_ptr), dev(col)
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+
+    def realization():
+        ccl.label_csr_philox(rp, dc, seed, gen.STREAM_OCC, p, out=lab, workspace=ws, stream=s)
+        return ccl.cluster_sizes(lab, stream=s)
+
+    want_lab = oracle.label_csr(n, row_ptr, col, gen.bernoulli(seed, m, p))
+    want_sizes = oracle.sizes_by_minimum(want_lab)
+    with torch.cuda.stream(s):
+        sizes = realization()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lab.cpu().numpy(), want_lab)
+    np.testing.assert_array_equal(sizes.cpu().numpy(), want_sizes)
+    g = torch.cuda.CUDAGraph()
+    _say("drawn-occupancy graph capture")
+    with torch.cuda.graph(g, stream=s):
+        captured = realization()
+    for r in range(3):
+        lab.fill_(-7)
+        captured.fill_(-5)
+        ws.fill_(0xAB)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(lab.cpu().numpy(), want_lab, err_msg=f"replay {r}")
+        np.testing.assert_array_equal(captured.cpu().numpy(), want_sizes, err_msg=f"replay {r}")
+
+
 # ------------------------------------------------------------ checks & errors
 
 def test_validate(ccl):
