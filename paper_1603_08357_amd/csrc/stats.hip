@@ -151,49 +151,32 @@ ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int
 
 // ---------------------------------------------------------------- sizes
 
-// Sizes are counted per workgroup in an LDS table (open addressing on the
-// cluster minimum; a workgroup's span of kSzSpan sites has at most that many
-// distinct labels, so the table of twice as many slots never fills), runs
-// of equal labels inside a lane first, then one global atomic per distinct
-// label and workgroup: a cluster spanning the whole graph costs one atomic
-// per workgroup, not one per site.
+// Sizes in two passes over spans of kSzSpan sites, one workgroup per span.
+// Labels are cluster minima, so a label r that appears in span [b, b+S) with
+// r >= b has its own site r in that span: the span owns entry r.
+//   1. own: each span counts the sites labelled by its own entries in a
+//      direct-indexed LDS array and writes its whole range of `sizes` with
+//      plain stores (zero where the site is no minimum), so no fill is needed;
+//   2. foreign: each span counts the labels r < b (clusters whose minimum is
+//      in an earlier span) in an LDS hash table and adds them with one global
+//      atomic per distinct label, after pass 1 has written every entry.
+// Runs of equal labels inside a lane are counted first.  At the percolation
+// threshold most clusters are small and local: on the 2^26-site triangle
+// lattice 7.5 M of the 12.4 M (label, span) pairs are owned, so the global
+// atomics drop to the 4.9 M foreign ones.  Labels outside [0, n) are skipped.
 constexpr int kSzBlock = 512;
 constexpr int kSzPer = 8;
 constexpr int kSzSpan = kSzBlock * kSzPer;
-constexpr int kSzSlots = 2 * kSzSpan;
+constexpr int kSzSlots = 2 * kSzSpan;  // a span has at most kSzSpan distinct labels
 static_assert((kSzSlots & (kSzSlots - 1)) == 0, "power of two");
 
-__global__ void __launch_bounds__(kSzBlock) k_fill_zero(int64_t n, int32_t* __restrict__ a) {
-  const int64_t stride = (int64_t)gridDim.x * kSzBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kSzBlock + threadIdx.x; i < n; i += stride) a[i] = 0;
-}
-
-__global__ void __launch_bounds__(kSzBlock)
-    k_cluster_sizes(int64_t n, const int32_t* __restrict__ label, int32_t* sizes) {
-  __shared__ int32_t key[kSzSlots];
-  __shared__ uint32_t cnt[kSzSlots];
-  for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock) {
-    key[t] = -1;
-    cnt[t] = 0;
-  }
-  __syncthreads();
+// Calls add(label, count) once per run of equal labels among the lane's
+// kSzPer consecutive sites.
+template <class Add>
+__device__ __forceinline__ void lane_runs(int64_t n, const int32_t* __restrict__ label, Add add) {
   const int64_t base = (int64_t)blockIdx.x * kSzSpan + (int64_t)threadIdx.x * kSzPer;
   int32_t cur = -1;
   uint32_t run = 0;
-  auto add = [&](int32_t r, uint32_t c) {
-    if (r < 0 || r >= n) return;  // not a site id: skipped
-    uint32_t h = ((uint32_t)r * 2654435761u) & (kSzSlots - 1);
-    for (;;) {
-      int32_t seen = -1;
-      if (__hip_atomic_compare_exchange_strong(&key[h], &seen, r, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP) ||
-          seen == r) {
-        __hip_atomic_fetch_add(&cnt[h], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        return;
-      }
-      h = (h + 1) & (kSzSlots - 1);
-    }
-  };
   for (int k = 0; k < kSzPer; ++k) {
     const int64_t i = base + k;
     if (i >= n) break;
@@ -207,6 +190,48 @@ __global__ void __launch_bounds__(kSzBlock)
     }
   }
   if (run) add(cur, run);
+}
+
+__global__ void __launch_bounds__(kSzBlock)
+    k_sizes_own(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ sizes) {
+  __shared__ uint32_t cnt[kSzSpan];
+  for (int t = threadIdx.x; t < kSzSpan; t += kSzBlock) cnt[t] = 0;
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * kSzSpan;
+  lane_runs(n, label, [&](int32_t r, uint32_t c) {
+    const int64_t t = (int64_t)r - b;
+    if (t >= 0 && t < kSzSpan)
+      __hip_atomic_fetch_add(&cnt[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  });
+  __syncthreads();
+  const int32_t span = (int32_t)min((int64_t)kSzSpan, n - b);
+  for (int t = threadIdx.x; t < span; t += kSzBlock) sizes[b + t] = (int32_t)cnt[t];
+}
+
+__global__ void __launch_bounds__(kSzBlock)
+    k_sizes_foreign(int64_t n, const int32_t* __restrict__ label, int32_t* sizes) {
+  __shared__ int32_t key[kSzSlots];
+  __shared__ uint32_t cnt[kSzSlots];
+  for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock) {
+    key[t] = -1;
+    cnt[t] = 0;
+  }
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * kSzSpan;
+  lane_runs(n, label, [&](int32_t r, uint32_t c) {
+    if (r < 0 || r >= b) return;  // owned by this span, or not a site id
+    uint32_t h = ((uint32_t)r * 2654435761u) & (kSzSlots - 1);
+    for (;;) {
+      int32_t seen = -1;
+      if (__hip_atomic_compare_exchange_strong(&key[h], &seen, r, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP) ||
+          seen == r) {
+        __hip_atomic_fetch_add(&cnt[h], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+      }
+      h = (h + 1) & (kSzSlots - 1);
+    }
+  });
   __syncthreads();
   for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock)
     if (key[t] >= 0) atomicAdd(sizes + key[t], (int32_t)cnt[t]);
@@ -214,9 +239,11 @@ __global__ void __launch_bounds__(kSzBlock)
 
 ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes, hipStream_t s,
                                 const DeviceInfo& d) {
-  CCL_LAUNCH("ccl_fill_zero", k_fill_zero, grid_for(n, kSzBlock, 8, d), kSzBlock, 0, s, n, sizes);
-  CCL_LAUNCH("ccl_cluster_sizes", k_cluster_sizes, (unsigned)((n + kSzSpan - 1) / kSzSpan), kSzBlock,
-             0, s, n, label, sizes);
+  (void)d;
+  const unsigned spans = (unsigned)((n + kSzSpan - 1) / kSzSpan);
+  CCL_LAUNCH("ccl_sizes_own", k_sizes_own, spans, kSzBlock, 0, s, n, label, sizes);
+  if (spans > 1)
+    CCL_LAUNCH("ccl_sizes_foreign", k_sizes_foreign, spans, kSzBlock, 0, s, n, label, sizes);
   return CCL_OK;
 }
 
