@@ -171,16 +171,32 @@ constexpr int kSzSlots = 2 * kSzSpan;  // a span has at most kSzSpan distinct la
 static_assert((kSzSlots & (kSzSlots - 1)) == 0, "power of two");
 
 // Calls add(label, count) once per run of equal labels among the lane's
-// kSzPer consecutive sites.
+// kSzPer consecutive sites (two 16-byte loads when `vec`: label is 16-byte
+// aligned and the lane's sites are all below n).
+static_assert(kSzPer == 8, "a lane reads its sites as two int4");
 template <class Add>
-__device__ __forceinline__ void lane_runs(int64_t n, const int32_t* __restrict__ label, Add add) {
+__device__ __forceinline__ void lane_runs(int64_t n, const int32_t* __restrict__ label, bool vec,
+                                          Add add) {
   const int64_t base = (int64_t)blockIdx.x * kSzSpan + (int64_t)threadIdx.x * kSzPer;
+  int32_t lab[kSzPer];
+  int cnt = 0;
+  if (vec && base + kSzPer <= n) {
+    const int4 u = reinterpret_cast<const int4*>(label + base)[0];
+    const int4 v = reinterpret_cast<const int4*>(label + base)[1];
+    lab[0] = u.x; lab[1] = u.y; lab[2] = u.z; lab[3] = u.w;
+    lab[4] = v.x; lab[5] = v.y; lab[6] = v.z; lab[7] = v.w;
+    cnt = kSzPer;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSzPer; ++k) lab[k] = base + k < n ? label[base + k] : 0;
+    cnt = base >= n ? 0 : (int)min((int64_t)kSzPer, n - base);
+  }
   int32_t cur = -1;
   uint32_t run = 0;
+#pragma unroll
   for (int k = 0; k < kSzPer; ++k) {
-    const int64_t i = base + k;
-    if (i >= n) break;
-    const int32_t r = label[i];
+    if (k >= cnt) break;
+    const int32_t r = lab[k];
     if (r == cur) {
       ++run;
     } else {
@@ -193,12 +209,12 @@ __device__ __forceinline__ void lane_runs(int64_t n, const int32_t* __restrict__
 }
 
 __global__ void __launch_bounds__(kSzBlock)
-    k_sizes_own(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ sizes) {
+    k_sizes_own(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ sizes, bool vec) {
   __shared__ uint32_t cnt[kSzSpan];
   for (int t = threadIdx.x; t < kSzSpan; t += kSzBlock) cnt[t] = 0;
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * kSzSpan;
-  lane_runs(n, label, [&](int32_t r, uint32_t c) {
+  lane_runs(n, label, vec, [&](int32_t r, uint32_t c) {
     const int64_t t = (int64_t)r - b;
     if (t >= 0 && t < kSzSpan)
       __hip_atomic_fetch_add(&cnt[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -209,7 +225,7 @@ __global__ void __launch_bounds__(kSzBlock)
 }
 
 __global__ void __launch_bounds__(kSzBlock)
-    k_sizes_foreign(int64_t n, const int32_t* __restrict__ label, int32_t* sizes) {
+    k_sizes_foreign(int64_t n, const int32_t* __restrict__ label, int32_t* sizes, bool vec) {
   __shared__ int32_t key[kSzSlots];
   __shared__ uint32_t cnt[kSzSlots];
   for (int t = threadIdx.x; t < kSzSlots; t += kSzBlock) {
@@ -218,7 +234,7 @@ __global__ void __launch_bounds__(kSzBlock)
   }
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * kSzSpan;
-  lane_runs(n, label, [&](int32_t r, uint32_t c) {
+  lane_runs(n, label, vec, [&](int32_t r, uint32_t c) {
     if (r < 0 || r >= b) return;  // owned by this span, or not a site id
     uint32_t h = ((uint32_t)r * 2654435761u) & (kSzSlots - 1);
     for (;;) {
@@ -241,9 +257,10 @@ ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes,
                                 const DeviceInfo& d) {
   (void)d;
   const unsigned spans = (unsigned)((n + kSzSpan - 1) / kSzSpan);
-  CCL_LAUNCH("ccl_sizes_own", k_sizes_own, spans, kSzBlock, 0, s, n, label, sizes);
+  const bool vec = (reinterpret_cast<uintptr_t>(label) & 15) == 0;
+  CCL_LAUNCH("ccl_sizes_own", k_sizes_own, spans, kSzBlock, 0, s, n, label, sizes, vec);
   if (spans > 1)
-    CCL_LAUNCH("ccl_sizes_foreign", k_sizes_foreign, spans, kSzBlock, 0, s, n, label, sizes);
+    CCL_LAUNCH("ccl_sizes_foreign", k_sizes_foreign, spans, kSzBlock, 0, s, n, label, sizes, vec);
   return CCL_OK;
 }
 

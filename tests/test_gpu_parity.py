@@ -306,7 +306,8 @@ def test_cluster_statistics(ccl):
     e = torch.zeros(0, dtype=torch.int32, device="cuda")
     assert ccl.spans(dev(np.arange(10, dtype=np.int32)), e, dev(np.arange(3, dtype=np.int32))).item() == 0
     # labels and site ids outside [0, N) are skipped: ids -1, no size, no flag
-    n = 9000
+    # (N not a multiple of 8: the last lane of a span holds fewer sites)
+    n = 9003
     lab = np.arange(n, dtype=np.int32)
     lab[[5, 4097, 8999]] = [n + 5, -3, 2**31 - 1]
     valid = lab == np.arange(n)
@@ -317,6 +318,16 @@ def test_cluster_statistics(ccl):
     a = dev(np.array([-1, n, 0, 5], np.int32))
     assert ccl.spans(dev(lab), a, dev(np.array([n + 100, 0], np.int32))).item() == 1
     assert ccl.spans(dev(lab), a, dev(np.array([n + 100, -7, 5], np.int32))).item() == 0
+    # labels that are not 16-byte aligned (a view one element in) and a ragged
+    # length: the statistics read them element by element
+    g = gen.triangle_csr_realization(97, 0.3473, 4)
+    want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+    buf = dev(np.concatenate([[0], want]).astype(np.int32))
+    view = buf[1:]
+    assert view.data_ptr() % 16 != 0
+    ids, count, sizes, _ = _gpu_stats(ccl, view, np.zeros(1, np.int32), np.zeros(1, np.int32))
+    np.testing.assert_array_equal(ids, oracle.cluster_ids(want)[0])
+    np.testing.assert_array_equal(sizes, oracle.sizes_by_minimum(want))
 
 
 # ------------------------------------------- the paper's neighbour-list path
