@@ -283,6 +283,45 @@ def bench_edges(g, steps, warmup, cold=False):
     return out, res
 
 
+def bench_edges_monte_carlo(g, seed, steps, warmup):
+    """Realizations per second on an edge list with the occupancy drawn on
+    the device: a mask kernel (ccl_bernoulli) then ccl_label, against the draw
+    inside the merge kernel (ccl_label_philox); both label the same draws."""
+    import torch
+    import gen
+    import paper_1603_08357_amd as ccl
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    m = len(g.src)
+    occ = torch.empty(m, dtype=torch.uint8, device="cuda")
+    out = torch.empty(g.n_sites, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    k = [0]
+
+    def masked():
+        ccl.bernoulli(gen.mix_seed(seed, k[0]), gen.STREAM_OCC, m, g.p, out=occ, stream=stream)
+        ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
+        k[0] += 1
+
+    def drawn():
+        ccl.label_philox(src, dst, g.n_sites, gen.mix_seed(seed, k[0]), gen.STREAM_OCC, g.p, out=out,
+                         stream=stream)
+        k[0] += 1
+
+    res = {}
+    for name, fn in (("mask_kernel", masked), ("drawn_in_merge", drawn)):
+        ms, _ = time_steps(fn, steps, warmup, stream)
+        kern = traced_kernels(fn, steps)
+        res[name] = {"ms_per_realization": round(ms, 5), "realizations_per_s": round(1e3 / ms, 1),
+                     "kernels": {k_: round(v["mean_ms"], 5) for k_, v in kern.items()}}
+    ccl.bernoulli(gen.mix_seed(seed, 0), gen.STREAM_OCC, m, g.p, out=occ, stream=stream)
+    ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
+    sep = out.clone()
+    ccl.label_philox(src, dst, g.n_sites, gen.mix_seed(seed, 0), gen.STREAM_OCC, g.p, out=out, stream=stream)
+    res["labels_equal_mask_path"] = bool(torch.equal(sep, out))
+    return res
+
+
 def bench_ell(nn, occ, steps, warmup):
     """ccl_label_ell on a (z_max, n) neighbour list already on the host."""
     import torch
@@ -828,6 +867,12 @@ def main():
                 "ms_per_step": round(rb["ms"], 5), "path_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                 "warm_step_ms": rb["warm_step_ms"], "cold_step_ms": rb["cold_step_ms"],
                 "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()}}
+            if pp == 0.5:
+                try:
+                    extra["monte_carlo_random3reg_2^24_p0.5"] = bench_edges_monte_carlo(
+                        b, 3, args.steps, args.warmup)
+                except Exception as e:
+                    extra["monte_carlo_random3reg_2^24_p0.5"] = f"failed: {type(e).__name__}: {e}"
             del b
 
     line = {

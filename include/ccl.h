@@ -69,6 +69,19 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
                      const uint8_t* occupied, int32_t* labels_out, void* stream);
 
 /*
+ * ccl_label with the occupancy drawn inside the merge kernel instead of read
+ * from a mask: bond b is occupied when word b of the Philox4x32-10 stream
+ * (seed, stream_id) lies below floor(p 2^32), exactly the mask
+ * ccl_bernoulli(seed, stream_id, 0, n_bonds, p, ...) writes (the Monte-Carlo
+ * setting of section 4, with no mask in memory).  p is NaN:
+ * CCL_ERR_INVALID_VALUE; p <= 0: no bond occupied; p >= 1: every bond.  The
+ * other arguments and errors are ccl_label's.
+ */
+ccl_status ccl_label_philox(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,
+                            uint64_t seed, uint32_t stream_id, double p, int32_t* labels_out,
+                            void* stream);
+
+/*
  * Label the clusters of a graph given as the paper's padded neighbour list
  * (section 3): z_max entries per site, column-major, so neighbour k of site
  * i is nn_list[k*N + i].  Runs the paper's own four steps: (i) each site's

@@ -17,7 +17,7 @@ import numpy as np
 import torch  # first: the library then binds to the HIP runtime torch loaded
 
 __all__ = [
-    "CclError", "label", "label_csr", "label_csr_philox", "label_ell", "csr_workspace_bytes",
+    "CclError", "label", "label_philox", "label_csr", "label_csr_philox", "label_ell", "csr_workspace_bytes",
     "philox_u32", "bernoulli", "cluster_ids", "cluster_sizes", "spans", "Plan", "Tuning",
     "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
     "library_path", "version",
@@ -59,6 +59,7 @@ def _load():
     st = ctypes.c_int
     sig = {
         "ccl_label": (st, [i64, i64, P, P, P, P, P]),
+        "ccl_label_philox": (st, [i64, i64, P, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, P, P]),
         "ccl_label_csr_workspace_size": (sz, [i64, i64]),
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
         "ccl_label_csr_philox": (st, [i64, i64, P, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
@@ -141,6 +142,24 @@ def label(src: torch.Tensor, dst: torch.Tensor, n_sites: int, occ: torch.Tensor 
     pl = _dev_ptr(out, torch.int32, "out", n_sites, dev)
     with torch.cuda.device(dev):
         _check(_lib.ccl_label(n_sites, m, ps, pd, po, pl, _stream(stream, dev)), "ccl_label")
+    return out
+
+
+def label_philox(src: torch.Tensor, dst: torch.Tensor, n_sites: int, seed: int, stream_id: int, p: float,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """label with bond b occupied when word b of the Philox stream
+    (seed, stream_id) is below floor(p 2^32), drawn inside the merge kernel:
+    the labels of label(src, dst, n_sites, bernoulli(seed, stream_id, len(src), p))."""
+    dev = src.device
+    m = src.numel()
+    ps = _dev_ptr(src, torch.int32, "src", None, dev)
+    pd = _dev_ptr(dst, torch.int32, "dst", m, dev)
+    if out is None:
+        out = torch.empty(n_sites, dtype=torch.int32, device=dev)
+    pl = _dev_ptr(out, torch.int32, "out", n_sites, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_label_philox(n_sites, m, ps, pd, seed, stream_id, float(p), pl, _stream(stream, dev)),
+               "ccl_label_philox")
     return out
 
 

@@ -111,8 +111,9 @@ using namespace ccl;
 
 extern "C" {
 
-ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,
-                     const uint8_t* occupied, int32_t* labels_out, void* stream) {
+static ccl_status label_edges_checked(int64_t n_sites, int64_t n_bonds, const int32_t* src,
+                                      const int32_t* dst, const uint8_t* occupied,
+                                      const PhiloxOcc* draw, int32_t* labels_out, void* stream) {
   if (n_sites < 0 || n_sites > INT32_MAX || n_bonds < 0) return CCL_ERR_INVALID_VALUE;
   if (n_bonds > 0 && n_sites == 0) return CCL_ERR_INVALID_VALUE;  // no valid ids exist
   if (n_sites > 0 && labels_out == nullptr) return CCL_ERR_INVALID_VALUE;
@@ -125,8 +126,13 @@ ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
-  return launch_label_edges(n_sites, n_bonds, src, dst, occupied, labels_out, (hipStream_t)stream,
-                            *d);
+  return launch_label_edges(n_sites, n_bonds, src, dst, occupied, draw, labels_out,
+                            (hipStream_t)stream, *d);
+}
+
+ccl_status ccl_label(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,
+                     const uint8_t* occupied, int32_t* labels_out, void* stream) {
+  return label_edges_checked(n_sites, n_bonds, src, dst, occupied, nullptr, labels_out, stream);
 }
 
 size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds) {
@@ -178,6 +184,14 @@ ccl_status ccl_label_csr_philox(int64_t n_sites, int64_t n_bonds, const int32_t*
   const PhiloxOcc draw{seed, stream_id, occupancy_threshold(p)};
   return label_csr_checked(n_sites, n_bonds, row_ptr, col, nullptr, &draw, labels_out, workspace,
                            workspace_bytes, stream);
+}
+
+ccl_status ccl_label_philox(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,
+                            uint64_t seed, uint32_t stream_id, double p, int32_t* labels_out,
+                            void* stream) {
+  if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
+  const PhiloxOcc draw{seed, stream_id, occupancy_threshold(p)};
+  return label_edges_checked(n_sites, n_bonds, src, dst, nullptr, &draw, labels_out, stream);
 }
 
 ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,

@@ -89,12 +89,13 @@ __device__ __forceinline__ uint32_t xcd_block_id() {
 // Launchers (one translation unit each); arguments already validated.
 ccl_status launch_init(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const DeviceInfo& d);
-ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                              const uint8_t* occ, int32_t* label, hipStream_t s,
-                              const DeviceInfo& d);
 struct PhiloxOcc;
-// occ: a mask aligned with col, or NULL; draw (only with occ NULL): draw the
-// occupancy of bond e as word e of that Philox stream; both NULL: all occupied
+// occ: a mask aligned with the bonds (src/dst, or col), or NULL; draw (only
+// with occ NULL): draw the occupancy of bond e as word e of that Philox
+// stream; both NULL: all occupied
+ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                              const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
+                              hipStream_t s, const DeviceInfo& d);
 ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
                             const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
                             void* workspace, hipStream_t s, const DeviceInfo& d);

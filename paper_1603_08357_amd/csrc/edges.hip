@@ -1,6 +1,7 @@
 // Edge-list labeling: init (step i), bond-parallel merge (step iii,
 // Algorithm 1), flatten (step iv).  Paper, section 3.
 #include "common.hpp"
+#include "philox.hpp"
 #include "uf.hpp"
 
 namespace ccl {
@@ -31,10 +32,15 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ label, in
 // src/dst are 16-byte aligned and a lane takes four consecutive bonds with
 // 16-byte loads (occ 4-byte aligned: one 4-byte load), then requests the first parent of
 // all eight ends before chasing any of them.
-template <bool VEC, bool HAS_OCC>
+// OCC: every bond occupied (0), read from the mask (1), or drawn as word b of
+// the Philox stream for bond b (2; the mask ccl_bernoulli would write).
+constexpr int kEdgeOccAll = 0, kEdgeOccMask = 1, kEdgeOccDraw = 2;
+
+template <bool VEC, int OCC>
 __global__ void __launch_bounds__(kBlock)
     k_merge_edges(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                  const uint8_t* __restrict__ occ, int64_t m, int32_t* label) {
+                  const uint8_t* __restrict__ occ, int64_t m, int32_t* label, PhiloxOcc rng) {
+  constexpr bool HAS_OCC = OCC == kEdgeOccMask, DRAW = OCC == kEdgeOccDraw;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int64_t done = 0;
@@ -45,6 +51,7 @@ __global__ void __launch_bounds__(kBlock)
       const int4 v4 = reinterpret_cast<const int4*>(dst)[q];
       uint32_t o4 = 0x01010101u;
       if (HAS_OCC) o4 = reinterpret_cast<const uint32_t*>(occ)[q];  // byte j = bond 4q + j
+      if (DRAW) o4 = philox_occ4(rng, 4 * (uint64_t)q);            // one Philox block
       const int32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
       const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
       int32_t pu[4], pv[4];
@@ -65,7 +72,7 @@ __global__ void __launch_bounds__(kBlock)
     done = m4 << 2;
   }
   for (int64_t b = done + tid; b < m; b += stride) {
-    if (HAS_OCC && occ[b] == 0) continue;
+    if ((HAS_OCC && occ[b] == 0) || (DRAW && !philox_occupied(rng, (uint64_t)b))) continue;
     unite(label, src[b], dst[b]);
   }
 }
@@ -202,8 +209,8 @@ ccl_status launch_flatten(int64_t n, int32_t* label, hipStream_t s, const Device
 }
 
 ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                              const uint8_t* occ, int32_t* label, hipStream_t s,
-                              const DeviceInfo& d) {
+                              const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
+                              hipStream_t s, const DeviceInfo& d) {
   ccl_status st = launch_init(n, label, s, d);
   if (st != CCL_OK) return st;
   if (m > 0) {
@@ -213,14 +220,25 @@ ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const in
     const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(occ) & 3) == 0 && m >= 8 * lanes;
     const unsigned g = grid_for(vec ? (m + 3) / 4 : m, kBlock, 8, d);
+    const PhiloxOcc rng = draw != nullptr ? *draw : PhiloxOcc{0, 0, 0};
     if (vec && occ)
-      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, true>), g, kBlock, 0, s, src, dst, occ, m, label);
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, kEdgeOccMask>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
+    else if (vec && draw)
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, kEdgeOccDraw>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
     else if (vec)
-      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, false>), g, kBlock, 0, s, src, dst, occ, m, label);
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<true, kEdgeOccAll>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
     else if (occ)
-      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, true>), g, kBlock, 0, s, src, dst, occ, m, label);
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, kEdgeOccMask>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
+    else if (draw)
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, kEdgeOccDraw>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
     else
-      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, false>), g, kBlock, 0, s, src, dst, occ, m, label);
+      CCL_LAUNCH("ccl_merge_edges", (k_merge_edges<false, kEdgeOccAll>), g, kBlock, 0, s, src, dst, occ,
+                 m, label, rng);
   }
   return launch_flatten(n, label, s, d);
 }

@@ -150,6 +150,12 @@ def test_more_host_side_argument_errors(lib):
     assert lib.ccl_philox_u32(1, 0, 0, 0, None, None) == 0
     assert lib.ccl_bernoulli(1, 0, 0, 10, float("nan"), P(64), None) == INVALID
     assert lib.ccl_bernoulli(1, 0, 0, 10, 0.5, None, None) == INVALID
+    # ccl_label_philox: NaN probability, then ccl_label's own checks
+    assert lib.ccl_label_philox(10, 5, P(64), P(128), 1, 0, float("nan"), P(4096), None) == INVALID
+    assert lib.ccl_label_philox(-1, 5, P(64), P(128), 1, 0, 0.5, P(4096), None) == INVALID
+    assert lib.ccl_label_philox(10, 5, None, P(128), 1, 0, 0.5, P(4096), None) == INVALID
+    assert lib.ccl_label_philox(10, 5, P(4096), P(128), 1, 0, 0.5, P(4096 + 8), None) == INVALID
+    assert lib.ccl_label_philox(0, 0, None, None, 1, 0, 0.5, None, None) == 0
     # ccl_label_csr_philox: NaN probability, then ccl_label_csr's own checks
     rp, col, lab = P(1 << 20), P(1 << 24), P(1 << 28)
     assert lib.ccl_label_csr_philox(10, 30, rp, col, 1, 0, float("nan"), lab, None, 0, None) == INVALID

@@ -598,6 +598,25 @@ def test_monte_carlo_graph_replay(ccl):
             np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=f"replay {r}")
 
 
+def test_edges_with_drawn_occupancy(ccl):
+    """The edge-list merge drawing bond b's occupancy as word b of the Philox
+    stream labels exactly as the host-drawn mask does: a small honeycomb
+    (one bond per lane), a triangle lattice of 5.9 M bonds (four bonds per
+    lane, 16-byte loads) and a random 3-regular graph, plus p = 0 and 1."""
+    for g, seed in ((gen.honeycomb_realization(256, 0.6527, 1), 1),
+                    (gen.triangle_realization(1400, 0.3473, 6), 6),
+                    (gen.bethe_random_regular(1 << 18, 3, 0.5, 8), 8)):
+        for p in (g.p, 0.0, 1.0):
+            occ = gen.bernoulli(seed, len(g.src), p)
+            _say(f"ccl_label_philox {g.name} m={len(g.src)} p={p}")
+            out = ccl.label_philox(dev(g.src), dev(g.dst), g.n_sites, seed, gen.STREAM_OCC, p)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), oracle.label_edges(g.n_sites, g.src, g.dst, occ))
+    with pytest.raises(ccl.CclError) as e:
+        ccl.label_philox(dev(g.src), dev(g.dst), g.n_sites, 1, 0, float("nan"))
+    assert e.value.status == 1
+
+
 def test_drawn_occupancy_graph_replay(ccl):
     """The realization with its occupancy drawn inside the tile kernel
     (ccl_label_csr_philox) and its cluster sizes, captured in a HIP graph and
