@@ -17,9 +17,10 @@ constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint32_t hi_a = __umulhi(kPhiloxMulA, c.x), lo_a = kPhiloxMulA * c.x;
-    const uint32_t hi_b = __umulhi(kPhiloxMulB, c.z), lo_b = kPhiloxMulB * c.z;
-    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+    // both halves of each 32x32 product from one 64-bit product
+    const uint64_t pa = (uint64_t)kPhiloxMulA * c.x, pb = (uint64_t)kPhiloxMulB * c.z;
+    c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb, (uint32_t)(pa >> 32) ^ c.w ^ k1,
+                   (uint32_t)pa);
     k0 += kPhiloxWeylA;
     k1 += kPhiloxWeylB;
   }
