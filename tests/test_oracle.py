@@ -330,3 +330,36 @@ def test_descending_path_and_star():
     assert (lab[joined] == joined.min()).all() and lab[hub] == joined.min()
     lone = leaves[~occ.astype(bool)]
     np.testing.assert_array_equal(lab[lone], lone)
+
+
+def load_ell_cases():
+    """Cases of tests/golden/ell_step_i.txt as (name, n, z, nn[z, n], occ[z, n], expected arrays)."""
+    cases, cur = [], None
+    for row in read_golden("ell_step_i.txt"):
+        if row[0] == "case":
+            n, z = int(row[2]), int(row[3])
+            cur = dict(name=row[1], n=n, z=z, nn=np.full((z, n), -1, np.int32),
+                       occ=np.zeros((z, n), np.uint8))
+            cases.append(cur)
+        elif row[0] == "s":
+            i = int(row[1])
+            for k, entry in enumerate(row[2:]):
+                v, o = entry.split(":")
+                cur["nn"][k, i] = int(v)
+                cur["occ"][k, i] = int(o)
+        else:
+            cur[row[0]] = [int(x) for x in row[1:]]
+    return cases
+
+
+@pytest.mark.parametrize("case", load_ell_cases(), ids=lambda c: c["name"])
+def test_ell_steps_hand_worked(case):
+    """Step (i) takes the LOWEST occupied lower neighbour (section 3), not the
+    first or last listed, not the highest, and not an unoccupied one; step
+    (ii) and the whole schedule end where the hand-worked fixture says."""
+    n, z, nn, occ = case["n"], case["z"], case["nn"], case["occ"]
+    init = oracle.ell_init(n, z, nn, occ)
+    assert init.tolist() == case["step_i"]
+    assert oracle.ell_residual_left(n, z, nn, occ).tolist() == case["left"]
+    assert oracle.analysis(init).tolist() == case["after_ii"]
+    assert oracle.label_ell(n, z, nn.ravel(), occ.ravel()).tolist() == case["final"]

@@ -76,3 +76,52 @@ def test_unmutated_copy_passes_the_pins():
 def test_pins_reject_mutant(name):
     kw = MUTANTS[name]
     assert _pins_reject(lambda n, s, d, o: _uf_label(n, s, d, o, **kw)), name
+
+
+# ---- step (i) of the paper's schedule: the residual list's lowest entry
+
+def _ell_init_mutant(n, z, nn, occ, *, pick="lowest", ignore_occ=False, or_equal=False):
+    """oracle.ell_init's definition with one planted error: the entry taken
+    from the residual list ("highest", "first" or "last" listed instead of
+    the lowest), the mask ignored, or the site itself counted as lower."""
+    nn = np.asarray(nn).reshape(z, n)
+    on = np.ones(nn.shape, bool) if ignore_occ else np.asarray(occ).reshape(z, n) != 0
+    out = np.arange(n, dtype=np.int32)
+    for i in range(n):
+        lower = [int(nn[k, i]) for k in range(z)
+                 if on[k, i] and 0 <= nn[k, i] and (nn[k, i] <= i if or_equal else nn[k, i] < i)]
+        if not lower:
+            continue
+        out[i] = {"lowest": min, "highest": max, "first": lambda l: l[0], "last": lambda l: l[-1]}[pick](lower)
+    return out
+
+
+ELL_MUTANTS = {
+    "takes the highest lower neighbour": dict(pick="highest"),
+    "takes the first listed lower neighbour": dict(pick="first"),
+    "takes the last listed lower neighbour": dict(pick="last"),
+    "ignores the occupancy mask": dict(ignore_occ=True),
+}
+
+
+def _ell_pins_reject(fn) -> bool:
+    from test_oracle import load_ell_cases
+
+    for case in load_ell_cases():
+        got = fn(case["n"], case["z"], case["nn"], case["occ"])
+        if got.tolist() != case["step_i"]:
+            return True
+        if oracle.analysis(got).tolist() != case["after_ii"]:
+            return True
+    return False
+
+
+def test_unmutated_ell_init_passes_the_pins():
+    assert not _ell_pins_reject(lambda n, z, nn, o: _ell_init_mutant(n, z, nn, o))
+    assert not _ell_pins_reject(oracle.ell_init)
+
+
+@pytest.mark.parametrize("name", sorted(ELL_MUTANTS))
+def test_pins_reject_ell_init_mutant(name):
+    kw = ELL_MUTANTS[name]
+    assert _ell_pins_reject(lambda n, z, nn, o: _ell_init_mutant(n, z, nn, o, **kw)), name
