@@ -3,7 +3,8 @@
 For one batch layout (instance offsets) and its device buffers, time a grid of
 ``ccl_tuning`` candidates -- workgroup size, resident workgroups per CU, work
 item sizes, the LDS small-instance path and the fused / phased schedule --
-keep only candidates whose labels equal those of the first candidate, and
+keep only candidates whose labels equal a reference labeling (by default the
+one-launch-per-instance schedule) and whose plan reports no error, and
 return the fastest.  Results are cached in a JSON file keyed by the device
 name and a coarse description of the layout (instance count and size
 quantiles), so later runs on the same kind of batch skip the search.
@@ -94,8 +95,14 @@ def _time_plan(plan, src, dst, occ, out, reps: int) -> float:
 
 
 def tune(site_off, bond_off, src, dst, occ, space=None, reps: int = 3, use_cache: bool = True,
-         limit: int | None = None, verbose: bool = False) -> dict:
-    """Best tuning (a dict of ccl_tuning fields) for this batch layout."""
+         limit: int | None = None, verbose: bool = False, reference=None) -> dict:
+    """Best tuning (a dict of ccl_tuning fields) for this batch layout.
+
+    Every candidate's labels are compared with `reference` (device int32
+    labels of the whole batch); when None, the reference is the one-launch-
+    per-instance schedule (ccl_label per instance: a different kernel path
+    from the batched kernel).  A candidate whose plan reports an error, or
+    whose labels differ, is never chosen."""
     dev_name = torch.cuda.get_device_name()
     key = f"{dev_name}|{layout_key(site_off)}"
     cache = _load_cache() if use_cache else {}
@@ -103,7 +110,9 @@ def tune(site_off, bond_off, src, dst, occ, space=None, reps: int = 3, use_cache
         return dict(cache[key]["tuning"])
     n = int(np.asarray(site_off)[-1])
     out = torch.empty(n, dtype=torch.int32, device=src.device)
-    ref = None
+    if reference is None:
+        reference = ccl.label_batched_per_instance(site_off, bond_off, src, dst, occ)
+        torch.cuda.synchronize()
     results = []
     for t in candidates(space, limit):
         try:
@@ -111,11 +120,7 @@ def tune(site_off, bond_off, src, dst, occ, space=None, reps: int = 3, use_cache
         except ccl.CclError:
             continue
         ms = _time_plan(plan, src, dst, occ, out, reps)
-        ok = plan.check() == 0
-        if ref is None:
-            ref = out.clone()
-        else:
-            ok = ok and bool(torch.equal(out, ref))
+        ok = plan.check() == 0 and bool(torch.equal(out, reference))
         plan.close()
         results.append((ms, ok, t))
         if verbose:

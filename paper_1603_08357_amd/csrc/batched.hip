@@ -110,8 +110,8 @@ __device__ __forceinline__ void signal_done(int32_t* ctr) {
 __global__ void k_batched_reset(uint32_t* head, int64_t n_head, int32_t* done, int64_t n_done) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = tid; i < n_head; i += stride) head[i] = 0;
-  for (int64_t i = tid; i < n_done; i += stride) done[i] = 0;
+  for (int64_t i = tid; i < n_head; i += stride) st_dev(head + i, 0u);
+  for (int64_t i = tid; i < n_done; i += stride) st_dev(done + i, 0);
 }
 
 __global__ void k_batched(BatchArgs a) {
@@ -163,11 +163,11 @@ __global__ void k_batched(BatchArgs a) {
         lds16_unite_lockstep<kLockstep, 2>(par, u, v);
       }
       __syncthreads();
-      for (int32_t i = threadIdx.x; i < n; i += blockDim.x) lab[i] = lds16_find(par, i);
+      for (int32_t i = threadIdx.x; i < n; i += blockDim.x) st_dev(lab + i, lds16_find(par, i));
     } else if (kind == kItemInit) {
       const int32_t lo = c * a.sites_per_chunk;
       const int32_t hi = (int32_t)min((int64_t)lo + a.sites_per_chunk, (int64_t)n);
-      for (int32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) lab[i] = i;
+      for (int32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) st_dev(lab + i, i);
       if (a.fused) signal_done(a.init_done + k);
     } else if (kind == kItemMerge) {
       const bool go =

@@ -18,6 +18,7 @@
 // larger than the site, so kernels 2-3 see a valid forest and finish the job
 // exactly as the single-pass method would.
 #include "common.hpp"
+#include "mem.hpp"
 #include "philox.hpp"
 #include "uf.hpp"
 
@@ -34,29 +35,6 @@ static_assert(4 * kGroupsPerIter < (1 << kLeaveBits) && kRowsPerThread * kDegFas
               "a lane's leaving bonds per step must fit a count of kLeaveBits bits");
 constexpr int kLdsRounds = 4;  // lockstep pointer-following rounds in LDS before the fallbacks
 static_assert((1 << kTileShift) == kCsrTile, "tile size");
-
-// Raw buffer loads (gfx9 buffer resource, 32-bit offsets): an offset past
-// the resource's byte size returns 0 instead of faulting, so every load of a
-// batch can be issued unconditionally and the compiler keeps them in flight
-// together instead of guarding each one with a branch and a wait.
-constexpr uint32_t kBufWord3 = 0x00020000;
-constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // beyond any resource used here
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, (int)kBufWord3);
-}
-__device__ __forceinline__ int32_t buf_i32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
-}
-__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
-}
-__device__ __forceinline__ uint32_t buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)byte_off, 0, 0);
-}
-__device__ __forceinline__ int4 buf_i32x4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
-  return make_int4((int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]);
-}
 
 // Tile-relative row of tile-relative bond e in an affine tile of degree d,
 // as e * ceil(2^20 / d) >> 20 (exact for d <= 4 and e < 2^18, which a tile of
@@ -274,7 +252,7 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             if ((leave >> (4 * u + j)) & 1u)
-              my_pairs[slot++] = make_int2((int32_t)(lo + affine_row(e + j, magic)), c4[j]);
+              st_dev2(my_pairs + slot++, make_int2((int32_t)(lo + affine_row(e + j, magic)), c4[j]));
         }
       }
 #pragma unroll
@@ -306,7 +284,7 @@ __global__ void __launch_bounds__(kTileBlock)
         if (tile_bond(par, affine_row(x, magic), v, lo, cnt)) {
           const uint32_t sl =
               __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          my_pairs[sl] = make_int2((int32_t)(lo + affine_row(x, magic)), v);
+          st_dev2(my_pairs + sl, make_int2((int32_t)(lo + affine_row(x, magic)), v));
         }
       }
     }
@@ -365,7 +343,7 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
           for (int j = 0; j < kDegFast; ++j)
             if ((leave >> (kDegFast * k + j)) & 1u)
-              my_pairs[slot++] = make_int2((int32_t)(lo + base + k * kTileBlock + tid), cv[k][j]);
+              st_dev2(my_pairs + slot++, make_int2((int32_t)(lo + base + k * kTileBlock + tid), cv[k][j]));
       }
       // rows longer than kDegFast: the rest of their bonds one by one
 #pragma unroll
@@ -379,7 +357,7 @@ __global__ void __launch_bounds__(kTileBlock)
           if (tile_bond(par, t, v, lo, cnt)) {
             const uint32_t sl =
                 __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            my_pairs[sl] = make_int2((int32_t)(lo + t), v);
+            st_dev2(my_pairs + sl, make_int2((int32_t)(lo + t), v));
           }
         }
       }
@@ -395,6 +373,7 @@ __global__ void __launch_bounds__(kTileBlock)
   // the tile), eight sites per lane resolved together and stored 16 bytes at
   // a time when the label array allows it
   const int32_t n4 = ((reinterpret_cast<uintptr_t>(label + lo) & 15) == 0) ? (cnt >> 2) : 0;
+  const __amdgpu_buffer_rsrc_t rl = make_rsrc(label + lo, 16u * (uint32_t)n4);
   for (int32_t q0 = 0; q0 < n4; q0 += 2 * kTileBlock) {
     int32_t x[8];
 #pragma unroll
@@ -420,12 +399,12 @@ __global__ void __launch_bounds__(kTileBlock)
       const int32_t q = q0 + h * kTileBlock + tid;
       const int32_t b = (int32_t)lo;
       if (q < n4)
-        reinterpret_cast<int4*>(label + lo)[q] =
-            make_int4(b + x[4 * h], b + x[4 * h + 1], b + x[4 * h + 2], b + x[4 * h + 3]);
+        st_dev4(rl, 16u * (uint32_t)q,
+                make_int4(b + x[4 * h], b + x[4 * h + 1], b + x[4 * h + 2], b + x[4 * h + 3]));
     }
   }
-  for (int t = 4 * n4 + tid; t < cnt; t += kTileBlock) label[lo + t] = (int32_t)(lo + lds16_find(par, t));
-  if (tid == 0 && seg != nullptr) seg[blockIdx.x] = make_int2(e_begin - e0, (int32_t)n_out);
+  for (int t = 4 * n4 + tid; t < cnt; t += kTileBlock) st_dev(label + lo + t, (int32_t)(lo + lds16_find(par, t)));
+  if (tid == 0 && seg != nullptr) st_dev2(seg + blockIdx.x, make_int2(e_begin - e0, (int32_t)n_out));
 }
 
 // Cross kernel: one workgroup per tile (tiles renumbered so that each XCD
@@ -583,6 +562,12 @@ __global__ void __launch_bounds__(kCrossBlock)
 // the window (every thread sharing that parent then finds the root in LDS).
 // Every value written is the site's final root; the window goes back with
 // 16-byte stores.  Windows are renumbered so each XCD takes a contiguous run.
+// These are the only plain (not device-scope) label stores of the CSR path:
+// they are the call's final values, no later kernel of the call writes or
+// atomically updates these words, and every writer of a word stores the same
+// root.  Device-scope stores here cost 0.035 ms on the 2^26-site lattice
+// (write-through of lines the window has just read), and 0.14 ms more for
+// the scattered parent stores.
 constexpr int kFlatWin = 16384;
 constexpr int kFlatBlock = 1024;
 constexpr int kFlatPer = 8;  // sites a lane resolves in lockstep
@@ -647,7 +632,7 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, i
         if (pin[k] < (uint32_t)cnt)
           lds_st(w + pin[k], x[k]);
         else
-          lab_st(label + p[k], x[k]);
+          label[p[k]] = x[k];  // a final root, as every writer of p stores
       }
       lds_st(w + t, x[k]);
     }

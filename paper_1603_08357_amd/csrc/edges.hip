@@ -1,6 +1,7 @@
 // Edge-list labeling: init (step i), bond-parallel merge (step iii,
 // Algorithm 1), flatten (step iv).  Paper, section 3.
 #include "common.hpp"
+#include "mem.hpp"
 #include "philox.hpp"
 #include "uf.hpp"
 
@@ -16,15 +17,18 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ label, in
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   int64_t done = 0;
   if (VEC) {
+    // device-scope 16-byte stores through a resource based at the
+    // workgroup's first group of each step (wavefront-uniform)
     const int64_t n4 = n >> 2;
-    int4* l4 = reinterpret_cast<int4*>(label);
-    for (int64_t q = tid; q < n4; q += stride) {
+    for (int64_t q0 = (int64_t)blockIdx.x * kBlock; q0 < n4; q0 += stride) {
+      const int64_t q = q0 + threadIdx.x;
       const int32_t b = (int32_t)(q << 2);
-      l4[q] = make_int4(b, b + 1, b + 2, b + 3);
+      const __amdgpu_buffer_rsrc_t r = make_rsrc(label + 4 * q0, 16u * (uint32_t)min<int64_t>(kBlock, n4 - q0));
+      st_dev4(r, 16u * threadIdx.x, make_int4(b, b + 1, b + 2, b + 3));
     }
     done = n4 << 2;
   }
-  for (int64_t i = done + tid; i < n; i += stride) label[i] = (int32_t)i;
+  for (int64_t i = done + tid; i < n; i += stride) st_dev(label + i, (int32_t)i);
 }
 
 // Step (iii): roots of both ends of every occupied bond, then the atomicMin
@@ -94,6 +98,10 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
   const int64_t g0 = (int64_t)xcd_block_id() * per;
   const int64_t g1 = min(g0 + per, groups);
   const int64_t full = VEC ? (n >> 2) : 0;  // groups with all four sites in range
+  // the workgroup's groups [g0, min(g1, full)) for its 16-byte stores (at most
+  // 2^18 groups, so the byte offsets fit 32 bits)
+  const __amdgpu_buffer_rsrc_t rl =
+      make_rsrc(label + 4 * g0, 16u * (uint32_t)max<int64_t>(0, min(g1, full) - g0));
   for (int64_t gb = g0; gb < g1; gb += G * kBlock) {
     int4 v[G];
     int32_t q[G][4];
@@ -103,7 +111,8 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
       // clamped index keeps the loads unconditional; groups outside the
       // vector range are replaced by the identity (nothing to do)
       const int64_t g = gb + j * kBlock + threadIdx.x;
-      const int4 ld = reinterpret_cast<const int4*>(label)[full > 0 ? min(g, full - 1) : 0];
+      int4 ld = make_int4(0, 0, 0, 0);
+      if (full > 0) ld = reinterpret_cast<const int4*>(label)[min(g, full - 1)];  // uniform branch
       const bool in = g < g1 && g < full;
       v[j] = in ? ld : make_int4((int32_t)(4 * g), (int32_t)(4 * g + 1), (int32_t)(4 * g + 2),
                                  (int32_t)(4 * g + 3));
@@ -170,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_flatten(int32_t* label, int64_t n) {
             if (x[j][t] != q[j][t]) lab_st(label + c[t], x[j][t]);  // the parent's root
             c[t] = x[j][t];
           }
-          reinterpret_cast<int4*>(label)[g] = v[j];
+          st_dev4(rl, 16u * (uint32_t)(g - g0), v[j]);
         }
       } else {
         for (int64_t i = i0; i < min(i0 + 4, n); ++i) {

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kEllBlock)
                int32_t* __restrict__ label) {
   const int64_t stride = (int64_t)gridDim.x * kEllBlock;
   for (int64_t i = (int64_t)blockIdx.x * kEllBlock + threadIdx.x; i < n; i += stride)
-    label[i] = ell_lowest<HAS_OCC>(n, z, nn, occ, i);
+    st_dev(label + i, ell_lowest<HAS_OCC>(n, z, nn, occ, i));
 }
 
 // Step (iii): Algorithm 1 for site i and each neighbour left on its residual

@@ -9,6 +9,7 @@
 // paper's cuRAND draws (section 4) so that a Monte-Carlo loop never moves a
 // mask across PCIe.
 #include "common.hpp"
+#include "mem.hpp"
 #include "philox.hpp"
 
 namespace ccl {
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(kRngBlock)
       uint32_t v = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) v |= (uint32_t)((uint64_t)word[j] < threshold) << (8 * j);
-      reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + (lo - first))[0] = v;
+      st_dev(reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + (lo - first)), v);
       continue;
     }
 #pragma unroll
@@ -42,9 +43,9 @@ __global__ void __launch_bounds__(kRngBlock)
       const uint64_t idx = (b << 2) + (uint64_t)j;
       if (idx < first || idx >= first + (uint64_t)n) continue;
       if (BYTES)
-        static_cast<uint8_t*>(out)[idx - first] = (uint64_t)word[j] < threshold ? 1 : 0;
+        st_dev(static_cast<uint8_t*>(out) + (idx - first), (uint8_t)((uint64_t)word[j] < threshold ? 1 : 0));
       else
-        static_cast<uint32_t*>(out)[idx - first] = word[j];
+        st_dev(static_cast<uint32_t*>(out) + (idx - first), word[j]);
     }
   }
 }

@@ -6,6 +6,7 @@
 //   * the spanning test: does one cluster hold a site of set A and one of B.
 // A site i is its cluster's minimum exactly when label[i] == i.
 #include "common.hpp"
+#include "mem.hpp"
 
 namespace ccl {
 
@@ -75,14 +76,17 @@ __global__ void __launch_bounds__(kIdBlock)
   const uint32_t run = block_exclusive_sum(s, scratch, &total);
   const int32_t r0 = (int32_t)run, r1 = r0 + (int32_t)f[0], r2 = r1 + (int32_t)f[1], r3 = r2 + (int32_t)f[2];
   if (whole) {
-    reinterpret_cast<int4*>(ids + base)[0] = make_int4(r0, r1, r2, r3);
+    // 16 bytes through a resource based at the workgroup's span (uniform)
+    const int64_t b0 = (int64_t)blockIdx.x * kIdSpan;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(ids + b0, 4u * (uint32_t)min((int64_t)kIdSpan, n - b0));
+    st_dev4(rs, 16u * threadIdx.x, make_int4(r0, r1, r2, r3));
   } else {
     const int32_t r[kIdPer] = {r0, r1, r2, r3};
 #pragma unroll
     for (int k = 0; k < kIdPer; ++k)
-      if (base + k < n) ids[base + k] = r[k];
+      if (base + k < n) st_dev(ids + base + k, r[k]);
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = (int32_t)total;
+  if (threadIdx.x == 0) st_dev(part + blockIdx.x, (int32_t)total);
 }
 
 // Exclusive scan of the per-workgroup counts, in one workgroup, chunk by
@@ -96,10 +100,10 @@ __global__ void __launch_bounds__(kIdBlock)
     const uint32_t v = j < n_parts ? (uint32_t)part[j] : 0u;
     uint32_t total;
     const uint32_t ex = block_exclusive_sum(v, scratch, &total);
-    if (j < n_parts) part[j] = (int32_t)(carry + ex);
+    if (j < n_parts) st_dev(part + j, (int32_t)(carry + ex));
     carry += total;
   }
-  if (threadIdx.x == 0) *n_clusters = (int32_t)carry;
+  if (threadIdx.x == 0) st_dev(n_clusters, (int32_t)carry);
 }
 
 // Adds each span's offset: ids[i] becomes the number of minima before i.
@@ -110,12 +114,14 @@ __global__ void __launch_bounds__(kIdBlock)
   if (vec && base + kIdPer <= n) {
     int4 v = reinterpret_cast<int4*>(ids + base)[0];
     v.x += off; v.y += off; v.z += off; v.w += off;
-    reinterpret_cast<int4*>(ids + base)[0] = v;
+    const int64_t b0 = (int64_t)blockIdx.x * kIdSpan;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(ids + b0, 4u * (uint32_t)min((int64_t)kIdSpan, n - b0));
+    st_dev4(rs, 16u * threadIdx.x, v);
     return;
   }
 #pragma unroll
   for (int k = 0; k < kIdPer; ++k)
-    if (base + k < n) ids[base + k] += off;
+    if (base + k < n) st_dev(ids + base + k, ids[base + k] + off);
 }
 
 // ids[i] = ids[label[i]]: a minimum's entry is its own id and is rewritten
@@ -132,13 +138,16 @@ __global__ void __launch_bounds__(kIdBlock)
   int64_t done = 0;
   if (vec) {
     const int64_t n4 = n >> 2;
-    for (int64_t q = tid; q < n4; q += stride) {
-      const int4 l = reinterpret_cast<const int4*>(label)[q];
-      reinterpret_cast<int4*>(ids)[q] = make_int4(id_of(l.x), id_of(l.y), id_of(l.z), id_of(l.w));
+    for (int64_t q0 = (int64_t)blockIdx.x * kIdBlock; q0 < n4; q0 += stride) {
+      const int64_t q = q0 + threadIdx.x;
+      // 16-byte stores through a resource based at the step's first group
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(ids + 4 * q0, 16u * (uint32_t)min((int64_t)kIdBlock, n4 - q0));
+      const int4 l = reinterpret_cast<const int4*>(label)[min(q, n4 - 1)];
+      if (q < n4) st_dev4(rs, 16u * threadIdx.x, make_int4(id_of(l.x), id_of(l.y), id_of(l.z), id_of(l.w)));
     }
     done = 4 * n4;
   }
-  for (int64_t i = done + tid; i < n; i += stride) ids[i] = id_of(label[i]);
+  for (int64_t i = done + tid; i < n; i += stride) st_dev(ids + i, id_of(label[i]));
 }
 
 size_t cluster_ids_workspace_bytes(int64_t n) {
@@ -166,7 +175,7 @@ ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int
 // r >= b has its own site r in that span: the span owns entry r.
 //   1. own: each span counts the sites labelled by its own entries in a
 //      direct-indexed LDS array and writes its whole range of `sizes` with
-//      plain stores (zero where the site is no minimum), so no fill is needed;
+//      non-atomic stores (zero where the site is no minimum), so no fill is needed;
 //   2. foreign: each span counts the labels r < b (clusters whose minimum is
 //      in an earlier span) in an LDS hash table and adds them with one global
 //      atomic per distinct label, after pass 1 has written every entry.
@@ -231,7 +240,7 @@ __global__ void __launch_bounds__(kSzBlock)
   });
   __syncthreads();
   const int32_t span = (int32_t)min((int64_t)kSzSpan, n - b);
-  for (int t = threadIdx.x; t < span; t += kSzBlock) sizes[b + t] = (int32_t)cnt[t];
+  for (int t = threadIdx.x; t < span; t += kSzBlock) st_dev(sizes + b + t, (int32_t)cnt[t]);
 }
 
 __global__ void __launch_bounds__(kSzBlock)
@@ -278,7 +287,7 @@ ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes,
 
 // flags[label[a]] = 1 for every site a of A; then any site b of B whose
 // cluster is flagged sets *result.  Site ids and labels outside [0, n) are
-// skipped.  Flag stores are plain byte stores of the
+// skipped.  Flag stores are byte stores of the
 // same value (races are benign); the flag array is cleared by a kernel, so
 // the sequence can be captured in a graph.
 constexpr int kSpBlock = 256;
@@ -286,8 +295,8 @@ constexpr int kSpBlock = 256;
 __global__ void __launch_bounds__(kSpBlock)
     k_span_clear(int64_t n, uint8_t* __restrict__ flags, int32_t* __restrict__ result) {
   const int64_t stride = (int64_t)gridDim.x * kSpBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += stride) flags[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *result = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += stride) st_dev(flags + i, (uint8_t)0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(result, 0);
 }
 
 __global__ void __launch_bounds__(kSpBlock)
@@ -297,7 +306,7 @@ __global__ void __launch_bounds__(kSpBlock)
   for (int64_t j = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; j < n_a; j += stride) {
     const int32_t i = a[j];
     const int32_t r = (i >= 0 && i < n) ? label[i] : -1;
-    if (r >= 0 && r < n) flags[r] = 1;
+    if (r >= 0 && r < n) st_dev(flags + r, (uint8_t)1);
   }
 }
 
@@ -311,7 +320,7 @@ __global__ void __launch_bounds__(kSpBlock)
     const int32_t r = (i >= 0 && i < n) ? label[i] : -1;
     hit = hit || (r >= 0 && r < n && flags[r] != 0);
   }
-  if (__any(hit) && (threadIdx.x & 63) == 0) *result = 1;
+  if (__any(hit) && (threadIdx.x & 63) == 0) st_dev(result, 1);
 }
 
 ccl_status launch_spans(int64_t n, const int32_t* label, int64_t n_a, const int32_t* a, int64_t n_b,

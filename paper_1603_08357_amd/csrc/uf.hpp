@@ -15,19 +15,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mem.hpp"
+
 namespace ccl {
 
 // ---------------------------------------------------------------- global
 
-// Ordinary cached global load/store of a label.  Wavefront-scope relaxed
-// atomics compile to plain global_load/global_store on gfx950; using them
-// keeps the compiler from caching a value across iterations of a chase.
+// Ordinary cached global load of a label.  A wavefront-scope relaxed atomic
+// load compiles to a plain global_load on gfx950; using it keeps the compiler
+// from caching a value across iterations of a chase.
 __device__ __forceinline__ int32_t lab_ld(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
-__device__ __forceinline__ void lab_st(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
+// A label store: device scope (see mem.hpp), so no later kernel's write of
+// the same word can be overtaken by it.
+__device__ __forceinline__ void lab_st(int32_t* p, int32_t v) { st_dev(p, v); }
 
 // Device-coherent atomicMin returning the previous value.
 __device__ __forceinline__ int32_t lab_min(int32_t* p, int32_t v) {
@@ -57,34 +59,31 @@ __device__ __forceinline__ int32_t find_root(const int32_t* label, int32_t x) {
   return x;
 }
 
-// The same chase with path halving: every visited site is re-pointed at its
+// The chase with path halving: every visited site is re-pointed at its
 // grandparent (a smaller member of the same cluster), so chains that many
 // concurrent joins stacked up shrink as threads walk them.  The store is an
 // atomicMin (lab_lower), so it never undoes a lower link another thread made.
 // For the merge step only: the flatten step stores nothing but final roots.
-__device__ __forceinline__ int32_t find_root_halving(int32_t* label, int32_t x) {
-  int32_t p = lab_ld(label + x);
-  while (p != x) {
-    const int32_t g = lab_ld(label + p);
-    if (g == p) return p;
-    lab_lower(label + x, g);
-    x = g;
-    p = lab_ld(label + x);
-  }
-  return x;
-}
-
-// find_root_halving for a chase whose first parent p = label[x] is already
-// loaded (lets a caller issue the first loads of several chases together).
+// This form starts from a first parent p = label[x] already loaded (lets a
+// caller issue the first loads of several chases together).
+// The compression atomic is issued after the load of the next link: one
+// counter tracks both on gfx950, so a wait for a load also waits for every
+// memory operation issued before it, and an atomic issued first would put
+// its round trip on the chase's critical path.
 __device__ __forceinline__ int32_t find_root_halving_from(int32_t* label, int32_t x, int32_t p) {
   while (p != x) {
     const int32_t g = lab_ld(label + p);
     if (g == p) return p;
+    const int32_t pg = lab_ld(label + g);
     lab_lower(label + x, g);
     x = g;
-    p = lab_ld(label + x);
+    p = pg;
   }
   return x;
+}
+
+__device__ __forceinline__ int32_t find_root_halving(int32_t* label, int32_t x) {
+  return find_root_halving_from(label, x, lab_ld(label + x));
 }
 
 // Join roots r1, r2 (any members work; roots save atomics): the label
@@ -134,9 +133,10 @@ __device__ __forceinline__ int32_t find_root_halving_checked(int32_t* label, int
       bad = true;
       return x;
     }
+    const int32_t pg = lab_ld(label + g);  // before the atomic, as above
     lab_lower(label + x, g);
     x = g;
-    p = lab_ld(label + x);
+    p = pg;
   }
   return x;
 }
@@ -247,18 +247,43 @@ __device__ __forceinline__ void lds16_st(uint16_t* p, int32_t v) {
 }
 
 
-// One masked-or per lane on the 32-bit LDS word at byte offset off (LDS
-// offsets are the low 32 bits of a generic pointer to shared memory): the
-// bits of mask take the values of bits, atomically, and the old word comes
-// back.  lds_wait completes it (the compiler does not count inline LDS
-// operations, so the wait is explicit and ties the result to it).
-__device__ __forceinline__ uint32_t lds_mskor_issue(uint32_t off, uint32_t mask, uint32_t bits) {
-  uint32_t r;
-  asm volatile("ds_mskor_rtn_b32 %0, %1, %2, %3" : "=v"(r) : "v"(off), "v"(mask), "v"(bits) : "memory");
-  return r;
-}
-__device__ __forceinline__ void lds_wait(uint32_t& r) {
-  asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(r) : : "memory");
+// Masked-or on 32-bit LDS words at byte offsets off[k] (LDS offsets are the
+// low 32 bits of a generic pointer to shared memory): the bits of mask[k]
+// take the values of bits[k], atomically, and the old words come back.  The
+// P operations are issued back to back and completed by one wait inside the
+// same asm statement, so every result is tied to its own wait (the compiler
+// does not count inline LDS operations).  P is 1, 2 or 4.
+template <int P>
+__device__ __forceinline__ void lds_mskor(uint32_t (&ret)[P], const uint32_t (&off)[P],
+                                          const uint32_t (&mask)[P], const uint32_t (&bits)[P]) {
+  static_assert(P == 1 || P == 2 || P == 4, "lds_mskor takes 1, 2 or 4 operations");
+  if constexpr (P == 1) {
+    asm volatile(
+        "ds_mskor_rtn_b32 %0, %1, %2, %3\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ret[0])
+        : "v"(off[0]), "v"(mask[0]), "v"(bits[0])
+        : "memory");
+  } else if constexpr (P == 2) {
+    asm volatile(
+        "ds_mskor_rtn_b32 %0, %2, %4, %6\n\t"
+        "ds_mskor_rtn_b32 %1, %3, %5, %7\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ret[0]), "=&v"(ret[1])
+        : "v"(off[0]), "v"(off[1]), "v"(mask[0]), "v"(mask[1]), "v"(bits[0]), "v"(bits[1])
+        : "memory");
+  } else {
+    asm volatile(
+        "ds_mskor_rtn_b32 %0, %4, %8, %12\n\t"
+        "ds_mskor_rtn_b32 %1, %5, %9, %13\n\t"
+        "ds_mskor_rtn_b32 %2, %6, %10, %14\n\t"
+        "ds_mskor_rtn_b32 %3, %7, %11, %15\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ret[0]), "=&v"(ret[1]), "=&v"(ret[2]), "=&v"(ret[3])
+        : "v"(off[0]), "v"(off[1]), "v"(off[2]), "v"(off[3]), "v"(mask[0]), "v"(mask[1]),
+          "v"(mask[2]), "v"(mask[3]), "v"(bits[0]), "v"(bits[1]), "v"(bits[2]), "v"(bits[3])
+        : "memory");
+  }
 }
 
 // atomicMin of entry x with v; returns the previous value of the entry
@@ -371,15 +396,15 @@ __device__ __forceinline__ void lds16_unite_lockstep(uint16_t* par, int32_t (&a)
     if (!__any(any)) break;
     // a lane with nothing left issues an empty mask on its own word, so all
     // P operations of every lane are in flight together
-    uint32_t ret[P], sh[P];
+    uint32_t ret[P], sh[P], off[P], msk[P], bits[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       sh[k] = (uint32_t)(hi[k] & 1) * 16u;
-      ret[k] = lds_mskor_issue(base + 4u * (uint32_t)(hi[k] >> 1), go[k] ? 0xFFFFu << sh[k] : 0u,
-                               go[k] ? (uint32_t)lo[k] << sh[k] : 0u);
+      off[k] = base + 4u * (uint32_t)(hi[k] >> 1);
+      msk[k] = go[k] ? 0xFFFFu << sh[k] : 0u;
+      bits[k] = go[k] ? (uint32_t)lo[k] << sh[k] : 0u;
     }
-#pragma unroll
-    for (int k = 0; k < P; ++k) lds_wait(ret[k]);
+    lds_mskor<P>(ret, off, msk, bits);
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int32_t old = (int32_t)((ret[k] >> sh[k]) & 0xFFFFu);

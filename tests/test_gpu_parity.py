@@ -110,6 +110,43 @@ def test_empty_and_degenerate(ccl):
     assert not gpu_edges(ccl, 33 * 33, src, dst).any()  # NULL mask: all occupied
 
 
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_small_and_unaligned_label_arrays(ccl, shift):
+    """Label arrays of 1-3 sites (fewer than one 16-byte group) and label
+    views starting 4, 8 or 12 bytes into an allocation (the unaligned
+    init and flatten paths), on the edge list, the neighbour list and CSR.
+    The view ends at the end of its allocation, so a read past it would
+    leave the buffer."""
+    rng = np.random.default_rng(60 + shift)
+    for n in (1, 2, 3, 5, 7, 1000, 70_001):
+        m = 3 * n
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        occ = (rng.random(m) < 0.4).astype(np.uint8)
+        want = oracle.label_edges(n, src, dst, occ)
+        _say(f"small/unaligned n={n} shift={shift}")
+        buf = torch.full((n + shift,), -5, dtype=torch.int32, device="cuda")
+        out = buf[shift:]
+        ccl.label(dev(src), dev(dst), n, dev(occ), out=out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        assert (buf[:shift].cpu().numpy() == -5).all()
+        nn, occ_ell = gen.ell_from_edges(n, src, dst, occ, int(np.bincount(
+            np.concatenate([src, dst]), minlength=n).max()))
+        buf.fill_(-5)
+        ccl.label_ell(dev(nn), dev(occ_ell), out=out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        order = np.argsort(src, kind="stable")
+        row_ptr = np.zeros(n + 1, np.int32)
+        np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+        buf.fill_(-5)
+        ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
+        ccl.label_csr(dev(row_ptr), dev(dst[order]), dev(occ[order]), out=out, workspace=ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
 # ------------------------------------------------------------ workloads
 
 def test_config1_honeycomb_l256(ccl):
@@ -735,44 +772,70 @@ def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
 # ------------------------------------------------------------ concurrency
 
 def test_concurrent_streams_match_oracle(ccl):
-    """Edge-list and CSR jobs in flight on eight streams at once: every
-    result equals the oracle's.  (A merge-step compression store landing
-    after the flatten's final root store showed up only under concurrent
-    kernels; compression stores are atomicMin for that reason.)"""
-    rng_graphs = []
+    """Edge-list, multi-tile CSR, neighbour-list (the paper's schedule) and
+    batched-plan jobs in flight on eight streams at once: every result equals
+    the oracle's.  (A merge-step compression store landing after the flatten's
+    final root store showed up only under concurrent kernels; every label
+    store of the labeling kernels is device-scope for that reason.)  Stops at
+    the first mismatch."""
+    jobs = []
     for i, (n, z, p) in enumerate([(300_000, 3, 0.5), (200_000, 4, 0.33), (150_000, 6, 0.2)]):
         g = gen.bethe_random_regular(n, z, p, 40 + i)
-        rng_graphs.append(("edges", g, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)))
+        jobs.append(("edges", g, oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)))
     for L, p in [(300, 0.3473), (512, 0.5209)]:
         g = gen.triangle_csr_realization(L, p, L)
-        rng_graphs.append(("csr", g, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)))
+        jobs.append(("csr", g, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)))
+    e = gen.bethe_random_regular(250_000, 3, 0.55, 47)
+    nn, occ_ell = gen.ell_from_edges(e.n_sites, e.src, e.dst, e.occ, 3)
+    jobs.append(("ell", (nn, occ_ell), oracle.label_edges(e.n_sites, e.src, e.dst, e.occ)))
+    specs = gen.batch_specs(24, base_seed=48, ls=(16, 64, 128, 256))
+    site_off, bond_off, bsrc, bdst, bocc = _batch(specs)
+    jobs.append(("batched", (site_off, bond_off, bsrc, bdst, bocc),
+                 oracle.label_batched(site_off, bond_off, bsrc, bdst, bocc)))
     S = 8
     streams = [torch.cuda.Stream() for _ in range(S)]
     bufs = []
-    for kind, g, _ in rng_graphs:
+    for kind, g, want in jobs:
+        ws = None
         if kind == "edges":
             ins = (dev(g.src), dev(g.dst), dev(g.occ))
-            ws = None
-        else:
+        elif kind == "csr":
             ins = (dev(g.row_ptr), dev(g.col), dev(g.occ))
             ws = [torch.empty(max(ccl.csr_workspace_bytes(g.n_sites, len(g.col)), 8), dtype=torch.uint8,
                               device="cuda") for _ in range(S)]
-        outs = [torch.empty(g.n_sites, dtype=torch.int32, device="cuda") for _ in range(S)]
+        elif kind == "ell":
+            ins = (dev(g[0]), dev(g[1]))
+        else:  # one plan per stream: a plan may be in flight on one stream at a time
+            ins = (dev(g[2]), dev(g[3]), dev(g[4]))
+            ws = [ccl.Plan(g[0], g[1]) for _ in range(S)]
+        outs = [torch.empty(len(want), dtype=torch.int32, device="cuda") for _ in range(S)]
         bufs.append((ins, ws, outs))
     torch.cuda.synchronize()
-    _say(f"concurrent: {len(rng_graphs)} graphs x {S} streams")
+    _say(f"concurrent: {len(jobs)} jobs (edge list, CSR, neighbour list, batched) x {S} streams")
     for it in range(40):
         picks = []
         for s in range(S):
-            gi = (it + s) % len(rng_graphs)
-            kind, g, _ = rng_graphs[gi]
+            gi = (it + s) % len(jobs)
+            kind, g, _ = jobs[gi]
             ins, ws, outs = bufs[gi]
             with torch.cuda.stream(streams[s]):
                 if kind == "edges":
                     ccl.label(ins[0], ins[1], g.n_sites, ins[2], out=outs[s], stream=streams[s])
-                else:
+                elif kind == "csr":
                     ccl.label_csr(ins[0], ins[1], ins[2], out=outs[s], workspace=ws[s], stream=streams[s])
+                elif kind == "ell":
+                    ccl.label_ell(ins[0], ins[1], out=outs[s], stream=streams[s])
+                else:
+                    ws[s].label(ins[0], ins[1], ins[2], out=outs[s], stream=streams[s])
             picks.append((s, gi))
         for s, gi in picks:
             streams[s].synchronize()
-            np.testing.assert_array_equal(bufs[gi][2][s].cpu().numpy(), rng_graphs[gi][2])
+            kind = jobs[gi][0]
+            np.testing.assert_array_equal(bufs[gi][2][s].cpu().numpy(), jobs[gi][2],
+                                          err_msg=f"iteration {it}, stream {s}, {kind} job")
+            if kind == "batched":
+                assert bufs[gi][1][s].check() == 0
+    for (kind, _, _), (_, ws, _) in zip(jobs, bufs):
+        if kind == "batched":
+            for plan in ws:
+                plan.close()
