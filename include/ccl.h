@@ -49,7 +49,8 @@ typedef enum {
   CCL_ERR_INDEX_OUT_OF_RANGE = 2, /* reported by the validation calls only */
   CCL_ERR_OUT_OF_MEMORY = 3,      /* plan creation could not allocate */
   CCL_ERR_HIP = 4,                /* a HIP call failed; see ccl_last_hip_error() */
-  CCL_ERR_NOT_SUPPORTED = 5       /* device is not gfx950 */
+  CCL_ERR_NOT_SUPPORTED = 5,      /* device is not gfx950 */
+  CCL_ERR_TOO_LARGE = 6           /* input exceeds a fixed capacity (no-allocation entry point) */
 } ccl_status;
 
 /* ---------------------------------------------------------------- labeling */
@@ -274,6 +275,23 @@ size_t ccl_cluster_ids_workspace_size(int64_t n_sites);
 ccl_status ccl_cluster_ids(int64_t n_sites, const int32_t* labels, int32_t* ids_out,
                            int32_t* n_clusters_out, void* workspace, size_t workspace_bytes,
                            void* stream);
+
+/*
+ * ccl_cluster_ids without a workspace argument and without any device
+ * allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace lives in a fixed device array of the library, 2 MiB per device,
+ * allocated when the library's code is loaded on that device and held until
+ * the process ends; it covers every n_sites up to
+ * ccl_cluster_ids_noalloc_max_sites() (INT32_MAX).  Larger n_sites:
+ * CCL_ERR_TOO_LARGE.  Nothing needs clearing between calls, but calls that
+ * overlap on one device share that array and race: serialize them (one
+ * stream, or events).  Kernel timing (ccl_trace_*) skips these launches.
+ * Arguments, results and other errors are ccl_cluster_ids's.
+ */
+size_t ccl_cluster_ids_noalloc_max_sites(void);
+ccl_status ccl_cluster_ids_noalloc(int64_t n_sites, const int32_t* labels, int32_t* ids_out,
+                                   int32_t* n_clusters_out, void* stream);
 
 /*
  * Cluster sizes indexed by the cluster's minimum site: sizes_out[r] is the

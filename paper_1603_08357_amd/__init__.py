@@ -18,7 +18,8 @@ import torch  # first: the library then binds to the HIP runtime torch loaded
 
 __all__ = [
     "CclError", "label", "label_philox", "label_csr", "label_csr_philox", "label_ell", "csr_workspace_bytes",
-    "philox_u32", "bernoulli", "cluster_ids", "cluster_sizes", "spans", "Plan", "Tuning",
+    "philox_u32", "bernoulli", "cluster_ids", "cluster_ids_noalloc", "cluster_sizes", "spans", "Plan",
+    "Tuning",
     "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
     "library_path", "version",
 ]
@@ -70,6 +71,8 @@ def _load():
                                P, P]),
         "ccl_cluster_ids_workspace_size": (sz, [i64]),
         "ccl_cluster_ids": (st, [i64, P, P, P, P, sz, P]),
+        "ccl_cluster_ids_noalloc_max_sites": (sz, []),
+        "ccl_cluster_ids_noalloc": (st, [i64, P, P, P, P]),
         "ccl_cluster_sizes": (st, [i64, P, P, P]),
         "ccl_spans": (st, [i64, P, i64, P, i64, P, P, P, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
@@ -230,6 +233,22 @@ def cluster_ids(labels: torch.Tensor, out: torch.Tensor | None = None, stream=No
         _check(_lib.ccl_cluster_ids(n, pl, po, _dev_ptr(count, torch.int32, "count"),
                                     _dev_ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream, dev)),
                "ccl_cluster_ids")
+    return out, count
+
+
+def cluster_ids_noalloc(labels: torch.Tensor, out: torch.Tensor, count: torch.Tensor, stream=None):
+    """cluster_ids into caller-provided `out` (int32, like labels) and `count`
+    (1-element int32) through ccl_cluster_ids_noalloc: no device memory is
+    allocated, by the library or here, so the call can be captured in a HIP
+    graph.  Calls that overlap on one device race (they share the library's
+    fixed workspace)."""
+    dev = labels.device
+    n = labels.numel()
+    pl = _dev_ptr(labels, torch.int32, "labels", None, dev)
+    po = _dev_ptr(out, torch.int32, "out", n, dev)
+    pc = _dev_ptr(count, torch.int32, "count", 1, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_cluster_ids_noalloc(n, pl, po, pc, _stream(stream, dev)), "ccl_cluster_ids_noalloc")
     return out, count
 
 

@@ -83,7 +83,12 @@ void clear_records_locked() {
 }
 }  // namespace
 
+static thread_local int g_no_trace = 0;
+NoTraceScope::NoTraceScope() { ++g_no_trace; }
+NoTraceScope::~NoTraceScope() { --g_no_trace; }
+
 TraceScope::TraceScope(const char* name, hipStream_t stream) {
+  if (g_no_trace > 0) return;
   std::lock_guard<std::mutex> lock(g_tr_mu);
   if (!g_tr_on || (int)g_tr.size() >= kMaxTrace) return;
   TraceRec r{name, pool_event(), pool_event()};
@@ -382,6 +387,8 @@ const char* ccl_status_string(ccl_status s) {
       return "CCL_ERR_HIP: a HIP call failed";
     case CCL_ERR_NOT_SUPPORTED:
       return "CCL_ERR_NOT_SUPPORTED: device is not gfx950";
+    case CCL_ERR_TOO_LARGE:
+      return "CCL_ERR_TOO_LARGE: input exceeds the fixed capacity of a no-allocation entry point";
   }
   return "unknown ccl_status";
 }

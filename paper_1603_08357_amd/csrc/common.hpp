@@ -36,6 +36,16 @@ class TraceScope {
   hipStream_t stream_ = nullptr;
 };
 
+// While one of these is alive on a host thread, TraceScope records nothing on
+// that thread (used where creating HIP events is not allowed).
+class NoTraceScope {
+ public:
+  NoTraceScope();
+  ~NoTraceScope();
+  NoTraceScope(const NoTraceScope&) = delete;
+  NoTraceScope& operator=(const NoTraceScope&) = delete;
+};
+
 // Grid for a grid-stride kernel: enough workgroups to cover `work` items at
 // `per_block` items each, capped at `per_cu` resident workgroups per CU.
 inline unsigned grid_for(int64_t work, int64_t per_block, int per_cu, const DeviceInfo& d) {

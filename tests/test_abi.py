@@ -54,7 +54,7 @@ def test_header_compiles_as_plain_c(tmp_path):
 
 
 def test_status_strings(lib):
-    for code in range(6):
+    for code in range(7):
         assert lib.ccl_status_string(code).startswith(b"CCL_")
     assert lib.ccl_version() == 100
 
