@@ -243,7 +243,7 @@ def roofline(kernels, bytes_fn, n, m, workload):
 
 # ---------------------------------------------------------------- workloads
 
-def bench_csr(L, p, seed, steps, warmup):
+def bench_csr(L, p, seed, steps, warmup, grid_width=0):
     import torch
     import gen
     import paper_1603_08357_amd as ccl
@@ -257,7 +257,7 @@ def bench_csr(L, p, seed, steps, warmup):
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream)
+    fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream, grid_width=grid_width)
     ms, wall = time_steps(fn, steps, warmup, stream)
     kern = traced_kernels(fn, steps)
     dist = step_distribution(fn, steps, stream)
@@ -447,12 +447,12 @@ def bench_monte_carlo(L, p, seed, steps, warmup):
 
     def one():
         ccl.bernoulli(gen.mix_seed(seed, k[0]), gen.STREAM_OCC, m, p, out=occ, stream=stream)
-        ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream)
+        ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream, grid_width=L)
         k[0] += 1
 
     def fused():
         ccl.label_csr_philox(rp, dc, gen.mix_seed(seed, k[0]), gen.STREAM_OCC, p, out=out,
-                             workspace=ws, stream=stream)
+                             workspace=ws, stream=stream, grid_width=L)
         k[0] += 1
 
     ms, _ = time_steps(one, steps, warmup, stream)
@@ -464,10 +464,10 @@ def bench_monte_carlo(L, p, seed, steps, warmup):
     head = occ[: 1 << 22].cpu().numpy()
     same = bool(np.array_equal(head, gen.bernoulli(gen.mix_seed(seed, 0), 1 << 22, p)))
     # and the draw inside the tile kernel labels as the drawn mask does
-    ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream)
+    ccl.label_csr(rp, dc, occ, out=out, workspace=ws, stream=stream, grid_width=L)
     sep = out.clone()
     ccl.label_csr_philox(rp, dc, gen.mix_seed(seed, 0), gen.STREAM_OCC, p, out=out, workspace=ws,
-                         stream=stream)
+                         stream=stream, grid_width=L)
     return {"ms_per_realization": round(ms, 5), "realizations_per_s": round(1e3 / ms, 1),
             "kernels": {k_: round(v["mean_ms"], 5) for k_, v in kern.items()},
             "device_mask_equals_host_generator": same,
@@ -789,7 +789,8 @@ def main():
     torch.cuda.set_device(0)
     log(f"device: {torch.cuda.get_device_name(0)}")
 
-    g, out, r = bench_csr(args.L, args.p, args.seed, args.steps, args.warmup)
+    # the lattice's ids number its rows of L sites: grid tiles (ccl_label_csr_grid)
+    g, out, r = bench_csr(args.L, args.p, args.seed, args.steps, args.warmup, grid_width=args.L)
     n, m = r["n"], r["m"]
     workload = f"triangle-csr L={args.L} p={args.p}"
     value = n / (r["ms"] * 1e-3) / 1e9
@@ -821,8 +822,17 @@ def main():
             extra["probe_copy"] = probe_copy()
         except Exception as e:  # measurement aid only
             extra["probe_copy"] = f"failed: {e}"
+        # the same labeling with slab tiles (65536 consecutive ids; ccl_label_csr)
+        gs, outs, rs = bench_csr(args.L, args.p, args.seed, max(5, args.steps // 2), args.warmup)
+        extra["slab_tiles"] = {"Gsites_s": round(rs["n"] / (rs["ms"] * 1e-3) / 1e9, 3),
+                               "ms_per_step": round(rs["ms"], 5),
+                               "kernels": {k: round(v["mean_ms"], 5) for k, v in rs["kernels"].items()},
+                               "labels_equal_grid_tiles": bool(torch.equal(outs, out))}
+        del gs, outs
+        torch.cuda.empty_cache()
         for pp in (0.1736, 0.5209):  # 0.5 p_c and 1.5 p_c of the same lattice
-            gp, outp, rp_ = bench_csr(args.L, pp, args.seed, max(5, args.steps // 2), args.warmup)
+            gp, outp, rp_ = bench_csr(args.L, pp, args.seed, max(5, args.steps // 2), args.warmup,
+                                      grid_width=args.L)
             extra[f"triangle_L{args.L}_p{pp}"] = {
                 "Gsites_s": round(rp_["n"] / (rp_["ms"] * 1e-3) / 1e9, 3),
                 "ms_per_step": round(rp_["ms"], 5), "step_ms": rp_["step_ms"],
@@ -890,7 +900,7 @@ def main():
         "data": "synthetic (seeded Philox bond occupancy)",
         "config": {"workload": f"triangle lattice L={args.L} periodic, bond percolation p={args.p}, "
                                "int32 half-CSR + uint8 mask, int32 labels",
-                   "n_sites": n, "n_bonds": m, "seed": args.seed},
+                   "n_sites": n, "n_bonds": m, "seed": args.seed, "grid_width": args.L},
         "roofline": rl,
         "cpu_baseline": cpu,
         "extra": extra,

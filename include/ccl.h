@@ -103,9 +103,10 @@ ccl_status ccl_label_ell(int64_t n_sites, int32_t z_max, const int32_t* nn_list,
                          const uint8_t* occupied, int32_t* labels_out, void* stream);
 
 /*
- * Workspace bytes ccl_label_csr needs: zero for n_sites <= 65536 (one tile),
- * else one 8-byte slot per bond (the bonds leaving their tile are collected
- * there) plus 8 bytes per 65536-site tile, rounded up to 256 bytes.
+ * Workspace bytes ccl_label_csr and ccl_label_csr_grid need (any grid width):
+ * zero for n_sites <= 65536 (one tile), else one 8-byte slot per bond (the
+ * bonds leaving their tile are collected there) plus a tile table of
+ * 8 (4 ceil(N / 65536) + 2) bytes rounded up to 256 bytes.
  */
 size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds);
 
@@ -136,6 +137,24 @@ ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_pt
                          void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * ccl_label_csr for a graph whose site ids number a grid row by row: site
+ * y*grid_width + x (a lattice of row length grid_width, as the paper's
+ * lattices are numbered).  The result does not depend on grid_width -- any
+ * CSR graph is labelled correctly with any value -- but the tiles follow the
+ * grid: 16 rows of 4096 columns instead of 65536 consecutive ids, so a tile
+ * has a shorter boundary and fewer bonds leave it (on the 8192-wide
+ * triangular lattice half as many).  Used when grid_width is a multiple of
+ * 4, larger than 4096 and smaller than n_sites with at least 16 rows;
+ * otherwise (grid_width = 0 included) this is ccl_label_csr.  grid_width < 0:
+ * CCL_ERR_INVALID_VALUE.  The other arguments, the workspace size and the
+ * errors are ccl_label_csr's.
+ */
+ccl_status ccl_label_csr_grid(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                              const int32_t* row_ptr, const int32_t* col, const uint8_t* occupied,
+                              int32_t* labels_out, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/*
  * ccl_label_csr with the occupancy drawn inside the tile kernel instead of
  * read from a mask: bond e (the entry col[e]) is occupied when word e of the
  * Philox4x32-10 stream (seed, stream_id) lies below floor(p 2^32), exactly
@@ -149,6 +168,12 @@ ccl_status ccl_label_csr_philox(int64_t n_sites, int64_t n_bonds, const int32_t*
                                 const int32_t* col, uint64_t seed, uint32_t stream_id, double p,
                                 int32_t* labels_out, void* workspace, size_t workspace_bytes,
                                 void* stream);
+
+/* ccl_label_csr_philox with the grid tiles of ccl_label_csr_grid. */
+ccl_status ccl_label_csr_grid_philox(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                                     const int32_t* row_ptr, const int32_t* col, uint64_t seed,
+                                     uint32_t stream_id, double p, int32_t* labels_out,
+                                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -65,6 +65,9 @@ def _load():
         "ccl_label_csr": (st, [i64, i64, P, P, P, P, P, sz, P]),
         "ccl_label_csr_philox": (st, [i64, i64, P, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
                                       P, P, sz, P]),
+        "ccl_label_csr_grid": (st, [i64, i64, i64, P, P, P, P, P, sz, P]),
+        "ccl_label_csr_grid_philox": (st, [i64, i64, i64, P, P, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.c_double, P, P, sz, P]),
         "ccl_label_ell": (st, [i64, i32, P, P, P, P]),
         "ccl_philox_u32": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, P, P]),
         "ccl_bernoulli": (st, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, ctypes.c_double,
@@ -308,29 +311,40 @@ def _csr_args(row_ptr, col, out, workspace):
 
 def label_csr(row_ptr: torch.Tensor, col: torch.Tensor, occ: torch.Tensor | None = None,
               out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-              stream=None) -> torch.Tensor:
+              stream=None, grid_width: int = 0) -> torch.Tensor:
     """Min-site-index cluster labels of a CSR graph; n_sites = len(row_ptr) - 1,
     bonds row_ptr[0] .. row_ptr[n]-1 of col (len(col) bounds their count).
     `workspace` (uint8, >= csr_workspace_bytes(n, len(col)) bytes) is
-    allocated when None."""
+    allocated when None.  `grid_width` > 0: the ids number a grid of that row
+    length row by row, and the tiles follow it (ccl_label_csr_grid); the
+    labels are the same for any value."""
     dev, n, m, prp, pc, out, pl, pw, wbytes = _csr_args(row_ptr, col, out, workspace)
     po = _dev_ptr(occ, torch.uint8, "occ", m, dev)
     with torch.cuda.device(dev):
-        _check(_lib.ccl_label_csr(n, m, prp, pc, po, pl, pw, wbytes, _stream(stream, dev)),
-               "ccl_label_csr")
+        if grid_width:
+            _check(_lib.ccl_label_csr_grid(n, m, int(grid_width), prp, pc, po, pl, pw, wbytes,
+                                           _stream(stream, dev)), "ccl_label_csr_grid")
+        else:
+            _check(_lib.ccl_label_csr(n, m, prp, pc, po, pl, pw, wbytes, _stream(stream, dev)),
+                   "ccl_label_csr")
     return out
 
 
 def label_csr_philox(row_ptr: torch.Tensor, col: torch.Tensor, seed: int, stream_id: int, p: float,
                      out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                     stream=None) -> torch.Tensor:
+                     stream=None, grid_width: int = 0) -> torch.Tensor:
     """label_csr with bond e occupied when word e of the Philox stream
     (seed, stream_id) is below floor(p 2^32), drawn inside the kernel: the
     labels of label_csr(row_ptr, col, bernoulli(seed, stream_id, len(col), p))."""
     dev, n, m, prp, pc, out, pl, pw, wbytes = _csr_args(row_ptr, col, out, workspace)
     with torch.cuda.device(dev):
-        _check(_lib.ccl_label_csr_philox(n, m, prp, pc, seed, stream_id, float(p), pl, pw, wbytes,
-                                         _stream(stream, dev)), "ccl_label_csr_philox")
+        if grid_width:
+            _check(_lib.ccl_label_csr_grid_philox(n, m, int(grid_width), prp, pc, seed, stream_id, float(p),
+                                                  pl, pw, wbytes, _stream(stream, dev)),
+                   "ccl_label_csr_grid_philox")
+        else:
+            _check(_lib.ccl_label_csr_philox(n, m, prp, pc, seed, stream_id, float(p), pl, pw, wbytes,
+                                             _stream(stream, dev)), "ccl_label_csr_philox")
     return out
 
 

@@ -145,11 +145,12 @@ size_t ccl_label_csr_workspace_size(int64_t n_sites, int64_t n_bonds) {
   return csr_workspace_bytes(n_sites, n_bonds);
 }
 
-static ccl_status label_csr_checked(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
-                                    const int32_t* col, const uint8_t* occupied,
-                                    const PhiloxOcc* draw, int32_t* labels_out, void* workspace,
-                                    size_t workspace_bytes, void* stream) {
-  if (n_sites < 0 || n_sites > INT32_MAX || n_bonds < 0 || n_bonds > INT32_MAX)
+static ccl_status label_csr_checked(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                                    const int32_t* row_ptr, const int32_t* col,
+                                    const uint8_t* occupied, const PhiloxOcc* draw,
+                                    int32_t* labels_out, void* workspace, size_t workspace_bytes,
+                                    void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX || n_bonds < 0 || n_bonds > INT32_MAX || grid_width < 0)
     return CCL_ERR_INVALID_VALUE;
   if (n_sites == 0) return CCL_OK;
   if (row_ptr == nullptr || labels_out == nullptr || (n_bonds > 0 && col == nullptr))
@@ -165,7 +166,7 @@ static ccl_status label_csr_checked(int64_t n_sites, int64_t n_bonds, const int3
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
-  return launch_label_csr(n_sites, row_ptr, col, occupied, draw, labels_out,
+  return launch_label_csr(n_sites, grid_width, row_ptr, col, occupied, draw, labels_out,
                           need ? workspace : nullptr, (hipStream_t)stream, *d);
 }
 
@@ -177,7 +178,25 @@ static uint64_t occupancy_threshold(double p) {
 ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_ptr,
                          const int32_t* col, const uint8_t* occupied, int32_t* labels_out,
                          void* workspace, size_t workspace_bytes, void* stream) {
-  return label_csr_checked(n_sites, n_bonds, row_ptr, col, occupied, nullptr, labels_out,
+  return label_csr_checked(n_sites, n_bonds, 0, row_ptr, col, occupied, nullptr, labels_out,
+                           workspace, workspace_bytes, stream);
+}
+
+ccl_status ccl_label_csr_grid(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                              const int32_t* row_ptr, const int32_t* col, const uint8_t* occupied,
+                              int32_t* labels_out, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  return label_csr_checked(n_sites, n_bonds, grid_width, row_ptr, col, occupied, nullptr,
+                           labels_out, workspace, workspace_bytes, stream);
+}
+
+static ccl_status label_csr_philox_checked(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                                           const int32_t* row_ptr, const int32_t* col, uint64_t seed,
+                                           uint32_t stream_id, double p, int32_t* labels_out,
+                                           void* workspace, size_t workspace_bytes, void* stream) {
+  if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
+  const PhiloxOcc draw{seed, stream_id, occupancy_threshold(p)};
+  return label_csr_checked(n_sites, n_bonds, grid_width, row_ptr, col, nullptr, &draw, labels_out,
                            workspace, workspace_bytes, stream);
 }
 
@@ -185,10 +204,16 @@ ccl_status ccl_label_csr_philox(int64_t n_sites, int64_t n_bonds, const int32_t*
                                 const int32_t* col, uint64_t seed, uint32_t stream_id, double p,
                                 int32_t* labels_out, void* workspace, size_t workspace_bytes,
                                 void* stream) {
-  if (p != p) return CCL_ERR_INVALID_VALUE;  // NaN
-  const PhiloxOcc draw{seed, stream_id, occupancy_threshold(p)};
-  return label_csr_checked(n_sites, n_bonds, row_ptr, col, nullptr, &draw, labels_out, workspace,
-                           workspace_bytes, stream);
+  return label_csr_philox_checked(n_sites, n_bonds, 0, row_ptr, col, seed, stream_id, p, labels_out,
+                                  workspace, workspace_bytes, stream);
+}
+
+ccl_status ccl_label_csr_grid_philox(int64_t n_sites, int64_t n_bonds, int64_t grid_width,
+                                     const int32_t* row_ptr, const int32_t* col, uint64_t seed,
+                                     uint32_t stream_id, double p, int32_t* labels_out,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+  return label_csr_philox_checked(n_sites, n_bonds, grid_width, row_ptr, col, seed, stream_id, p,
+                                  labels_out, workspace, workspace_bytes, stream);
 }
 
 ccl_status ccl_label_philox(int64_t n_sites, int64_t n_bonds, const int32_t* src, const int32_t* dst,

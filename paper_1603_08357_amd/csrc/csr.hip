@@ -43,6 +43,13 @@ __device__ __forceinline__ int32_t affine_row(int32_t e, uint32_t magic) {
   return (int32_t)(((uint64_t)(uint32_t)e * magic) >> 20);
 }
 
+// Site column of bond e of a tile row of degree d <= 4, as e * ceil(2^16 / d)
+// >> 16 with one 24-bit multiply: exact for e < 2^14 (a 4096-site row has at
+// most 16384 bonds); `magic16` is ceil(2^16 / d).
+__device__ __forceinline__ int32_t row_bond_site(int32_t e, uint32_t magic16) {
+  return (int32_t)(__umul24((uint32_t)e, magic16) >> 16);
+}
+
 // Join bond (t, v) of the tile (t tile-relative, v global) in LDS, or, when v
 // lies outside the tile, count it and return true (the caller records it).
 __device__ __forceinline__ bool tile_bond(uint16_t* par, int32_t t, int32_t v, int64_t lo,
@@ -407,6 +414,393 @@ __global__ void __launch_bounds__(kTileBlock)
   if (tid == 0 && seg != nullptr) st_dev2(seg + blockIdx.x, make_int2(e_begin - e0, (int32_t)n_out));
 }
 
+// ---------------------------------------------------------------- 2-D tiles
+//
+// Grid tiles.  When the site ids number a grid row by row (site y*W + x,
+// e.g. a lattice of row length W), a tile of 65536 consecutive ids is a slab
+// of 65536/W rows whose two long edges cross up to 2W bonds each way: on the
+// 8192-wide triangular lattice a quarter of the sites sit on a slab edge and
+// the cross kernel gets 5.8 M leaving bonds at p_c.  A grid tile is instead
+// kGridTh rows of kGridTw columns (16 x 4096): half the edge per site, so
+// half the leaving bonds, and in the 16-row tiles the clusters are still
+// small enough for the LDS union to stay cheap (taller tiles cost more in
+// the tile kernel than they save in the cross kernel).  Any CSR graph is
+// labelled correctly with any W; W only changes which bonds stay inside a
+// tile.  Tile (ty, tx) holds rows [16 ty, 16 ty + 16) and columns
+// [4096 tx, 4096 tx + cw); tile-relative slot t = (row << 12) | column, so
+// slot order is id order and the LDS roots are still the tile minima.
+// Tile-row ty's bonds form one contiguous range of the CSR, and tile tx of
+// that row takes the slots [start + bonds of columns < 4096 tx in each of its
+// rows, + its own bonds) of the pair list: the tiles' regions are disjoint
+// and exactly as large as their bond counts, for any CSR.
+constexpr int kGridTwShift = 12;
+constexpr int kGridTw = 1 << kGridTwShift;
+constexpr int kGridTh = kCsrTile / kGridTw;
+static_assert(kGridTh <= 64, "one lane per tile row in the header loads");
+
+struct GridGeo {
+  int64_t n;        // sites
+  int64_t w;        // row length of the id grid
+  int64_t h;        // rows, ceil(n / w)
+  int32_t tiles_x;  // tiles per tile-row, ceil(w / kGridTw)
+  float inv_w;      // 1 / w
+  int32_t w_shift;  // log2(w) when w is a power of two
+};
+
+// Sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+template <int OCC, bool POW2>
+__global__ void __launch_bounds__(kTileBlock)
+    k_csr_tile_grid(GridGeo geo, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                    const uint8_t* __restrict__ occ, int32_t* __restrict__ label,
+                    int2* __restrict__ pairs, int2* __restrict__ seg, PhiloxOcc rng) {
+  constexpr bool HAS_OCC = OCC == kOccMask, DRAW = OCC == kOccDraw;
+  __shared__ uint16_t par[kCsrTile];  // tile-relative parents, 16 bits each
+  __shared__ uint32_t stage[kTileBlock / 64][kStageCap];  // per-wavefront join staging
+  __shared__ uint32_t n_out;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  // Workgroup-uniform values are kept in scalar registers (readfirstlane):
+  // a buffer resource or loop bound the compiler took for divergent would
+  // cost a waterfall loop around every load and vector registers the stream
+  // needs.
+  auto uni = [](int32_t v) { return __builtin_amdgcn_readfirstlane(v); };
+  auto uni64 = [&](int64_t v) {
+    return (int64_t)(((uint64_t)(uint32_t)uni((int32_t)(v >> 32)) << 32) | (uint32_t)uni((int32_t)v));
+  };
+  const int32_t ty = (int32_t)blockIdx.x / geo.tiles_x;
+  const int32_t tx = (int32_t)blockIdx.x - ty * geo.tiles_x;
+  const int64_t y0 = (int64_t)ty * kGridTh;
+  const int64_t x0 = (int64_t)tx << kGridTwShift;
+  const int32_t cw = (int32_t)min((int64_t)kGridTw, geo.w - x0);
+  const int64_t u0 = y0 * geo.w + x0;
+  // sites of tile row s: [u0 + s w, + len(s)); the last grid row may be partial
+  auto seg_len = [&](int32_t s) -> int32_t {
+    const int64_t r = geo.n - (u0 + (int64_t)s * geo.w);
+    return r <= 0 ? 0 : (int32_t)min((int64_t)cw, r);
+  };
+  // rows of the tile-row, and those holding at least one site of this tile
+  // (only the last grid row can be short)
+  const int32_t rows_all = uni((int32_t)min((int64_t)kGridTh, geo.h - y0));
+  const int32_t rows = uni(rows_all > 0 && seg_len(rows_all - 1) == 0 ? rows_all - 1 : rows_all);
+  if (rows == 0) {  // no site of the partial last grid row falls in this tile
+    if (threadIdx.x == 0) st_dev2(seg + blockIdx.x, make_int2(0, 0));
+    return;
+  }
+  // header, computed by every wavefront on its own (lane s < rows: tile row s):
+  // the first bond of the tile-row, of the row and of the tile's segment of
+  // it, and the end of that segment
+  int32_t ra = 0, rb = 0, rc_end = 0, len_l = 0;
+  if (lane < rows_all) {
+    const int64_t row0 = min((y0 + lane) * geo.w, geo.n);
+    const int64_t us = min(row0 + x0, geo.n);
+    len_l = seg_len(lane);
+    ra = row_ptr[row0];
+    rb = row_ptr[us];
+    rc_end = row_ptr[us + len_l];
+  }
+  const int32_t e0 = row_ptr[0];
+  const int32_t tile_row_start = uni(__shfl(ra, 0, 64));
+  const int32_t e_first = uni(__shfl(rb, 0, 64));           // first bond of the tile
+  const int32_t e_last = uni(__shfl(rc_end, rows - 1, 64));  // one past its last bond
+  const int64_t before = uni64(wave_sum64(lane < rows_all ? (int64_t)(rb - ra) : 0));
+  const int64_t mine = uni64(wave_sum64(lane < rows_all ? (int64_t)(rc_end - rb) : 0));  // the tile's bonds
+  const int64_t tile_sites = uni64(wave_sum64((int64_t)len_l));
+  const int64_t region = (int64_t)(tile_row_start - e0) + before;  // the tile's pair-list slots
+  int2* my_pairs = pairs + region;
+  const int32_t len0 = uni(seg_len(0));
+  const int32_t len_last = uni(seg_len(rows - 1));  // every other tile row has cw sites
+  auto row_len = [&](int32_t s) { return s == rows - 1 ? len_last : (s < rows ? cw : 0); };
+  const int64_t span_sites = uni64((int64_t)(rows - 1) * geo.w + len_last);  // u0 .. last site + 1
+  const int32_t span_bonds = e_last - e_first;
+  const bool fast = uni(span_bonds >= 0 && span_bonds < (1 << 30) && span_sites < (1 << 29)) != 0;
+  // affine: row_ptr[u] = e_first + deg (u - u0) on every site of the tile.
+  // Tried when the first row, the whole span and the tile's own bonds all
+  // fit that degree (so the speculative pass never records more leaving
+  // bonds than the tile's region holds), then verified entry by entry.
+  const int32_t seg0_bonds = uni(__shfl(rc_end, 0, 64)) - e_first;
+  const int32_t deg = uni((fast && len0 > 0 && seg0_bonds % len0 == 0) ? seg0_bonds / len0 : 0);
+  const bool affine_try =
+      deg >= 1 && deg <= 4 && (int64_t)span_bonds == (int64_t)deg * span_sites &&
+      mine == (int64_t)deg * tile_sites &&
+      ((int64_t)deg * geo.w) % 4 == 0 &&
+      (!HAS_OCC || ((reinterpret_cast<uintptr_t>(occ + e_first) & 3) == 0));
+  const uint32_t magic16 = deg > 0 ? ((1u << 16) + (uint32_t)deg - 1u) / (uint32_t)deg : 0u;
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(row_ptr + u0, fast ? (uint32_t)(span_sites + 1) * 4u : 0u);
+  const __amdgpu_buffer_rsrc_t rcol = make_rsrc(col + e_first, fast ? (uint32_t)span_bonds * 4u : 0u);
+  const __amdgpu_buffer_rsrc_t ro =
+      make_rsrc(HAS_OCC ? occ + e_first : nullptr, fast && HAS_OCC ? (uint32_t)span_bonds : 0u);
+  const int32_t w32 = (int32_t)min(geo.w, (int64_t)INT32_MAX);
+  const int32_t row_base = (int32_t)(y0 * geo.w);  // < n <= 2^31 - 1
+  const uint32_t lim = (uint32_t)min((int64_t)rows * geo.w, (int64_t)UINT32_MAX);
+
+  // Tile slot of site v, or -1 when v lies outside the tile.  POW2: bit
+  // fields (below); otherwise a float quotient corrected by one step (exact:
+  // the row index within reach is below kGridTh).
+  // With w = 2^w_shift (>= 2 kGridTw), an id is (row, column) in bit fields,
+  // the tile is the ids whose bits above the low 12 of the column and above
+  // the low 4 of the row equal the tile's (mask pow2_m, pattern pow2_b), and
+  // the slot is those low bits side by side.
+  const uint32_t pow2_m = POW2 ? ~((uint32_t)(kGridTw - 1) | ((uint32_t)(kGridTh - 1) << geo.w_shift)) : 0u;
+  const uint32_t pow2_b = POW2 ? ((uint32_t)x0 | (uint32_t)(y0 << geo.w_shift)) : 0u;
+  auto slot_of = [&](int32_t v) -> int32_t {
+    if (POW2) {
+      const uint32_t uv = (uint32_t)v;
+      const uint32_t t = (((uv >> geo.w_shift) & (uint32_t)(kGridTh - 1)) << kGridTwShift) |
+                         (uv & (uint32_t)(kGridTw - 1));
+      return (uv & pow2_m) == pow2_b ? (int32_t)t : -1;
+    }
+    const uint32_t vr = (uint32_t)(v - row_base);
+    if (vr >= lim) return -1;
+    int32_t vs = (int32_t)((float)vr * geo.inv_w);
+    int32_t r = (int32_t)vr - vs * w32;
+    if (r < 0) {
+      --vs;
+      r += w32;
+    } else if (r >= w32) {
+      ++vs;
+      r -= w32;
+    }
+    const uint32_t vc = (uint32_t)(r - (int32_t)x0);
+    return vc < (uint32_t)cw ? (vs << kGridTwShift) | (int32_t)vc : -1;
+  };
+
+  // ---- the affine stream.  A tile row's bonds are [e_first + deg s w,
+  // + deg len(s)), read relative to the tile's first bond in groups of four;
+  // each row is padded to whole slots of kTileBlock groups (spr slots per
+  // row), so a slot -- one group per lane -- lies in a single row and its
+  // row index is a scalar.  Slot (k, u) of step k is G k + u.
+  const int32_t gps = (deg * cw + 3) >> 2;                        // groups per row
+  const int32_t spr = max(1, (gps + kTileBlock - 1) / kTileBlock);  // slots per row
+  const int32_t n_slots = rows * spr;
+  constexpr int G = kGroupsPerIter;
+  const int32_t iters = (n_slots + G - 1) / G;
+  int4 c[G], cn[G];
+  uint32_t o[G], on[G];
+  // a slot position (row s, slot r of the row), advanced without division
+  struct SlotPos {
+    int32_t s, r;
+  };
+  auto advance = [&](SlotPos p, int32_t by) {  // by <= G
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+      if (i < by && ++p.r == spr) {
+        p.r = 0;
+        ++p.s;
+      }
+    return p;
+  };
+  auto load = [&](SlotPos p, int4& cv, uint32_t& ov) {
+    const int32_t g = p.r * kTileBlock + tid;
+    const bool in = p.s < rows && 4 * g < deg * row_len(p.s);
+    const uint32_t off = in ? (uint32_t)(deg * p.s * w32 + 4 * g) : kOffNone;
+    cv = buf_i32x4(rcol, off * 4u);
+    ov = HAS_OCC ? buf_u32(ro, off)
+                 : (!in ? 0u : (DRAW ? philox_occ4(rng, (uint64_t)e_first + off) : 0x01010101u));
+  };
+  SlotPos next{0, 0};  // the slot of the next load
+  if (affine_try) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      load(next, c[u], o[u]);
+      next = advance(next, 1);
+    }
+  }
+
+  auto init_par = [&]() {
+    for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {  // par[t] = t, 16 bytes at a time
+      const uint32_t t = 8u * (uint32_t)w;
+      reinterpret_cast<uint4*>(par)[w] =
+          make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16),
+                     (t + 6) | ((t + 7) << 16));
+    }
+    if (tid == 0) n_out = 0;
+  };
+  init_par();
+  __syncthreads();
+
+  bool affine = false;
+  if (affine_try) {
+    // verification: every row_ptr entry of every tile row equals e_first +
+    // deg (u - u0): entries [0, len(s)) of row s in groups of four, one group
+    // per lane, vslots per row, one vslot per step (requested a step ahead,
+    // like the bonds, so no wait for it stands between a step's loads and its
+    // joins), the rest after the loop; then the end entry of each row
+    const int32_t rgps = (cw + 3) >> 2;
+    const int32_t vspr = max(1, (rgps + kTileBlock - 1) / kTileBlock);
+    const int32_t n_vslots = rows * vspr;
+    auto rp_at = [&](int32_t vslot, int32_t& rel, int32_t& n_ok) {
+      const int32_t s = vslot / vspr;  // scalar
+      const int32_t i = 4 * ((vslot - s * vspr) * kTileBlock + tid);
+      n_ok = vslot < n_vslots ? row_len(s) - i : 0;
+      rel = s * w32 + i;  // site offset from u0
+    };
+    auto rp_load = [&](int32_t vslot) {
+      int32_t rel, n_ok;
+      rp_at(vslot, rel, n_ok);
+      return buf_i32x4(rp, n_ok > 0 ? 4u * (uint32_t)rel : kOffNone * 4u);
+    };
+    auto rp_ok = [&](int32_t vslot, const int4& v) {
+      int32_t rel, n_ok;
+      rp_at(vslot, rel, n_ok);
+      const int32_t want = (int32_t)((uint32_t)e_first + (uint32_t)deg * (uint32_t)rel);
+      return n_ok <= 0 ||
+             ((v.x == want) && (n_ok < 2 || v.y == want + deg) && (n_ok < 3 || v.z == want + 2 * deg) &&
+              (n_ok < 4 || v.w == want + 3 * deg));
+    };
+    bool ok = true;
+    uint32_t staged = 0;  // entries on this wavefront's staging stack
+    int4 rv = rp_load(0), rvn;
+    SlotPos cur{0, 0};  // the slot of this step's first group
+    for (int32_t k = 0; k < iters; ++k) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        load(next, cn[u], on[u]);
+        next = advance(next, 1);
+      }
+      rvn = rp_load(k + 1);
+      ok = rp_ok(k, rv) && ok;
+      uint32_t leave = 0;  // bit 4u+j: bond j of group u leaves the tile
+      SlotPos at = cur;
+#pragma unroll
+      for (int u = 0; u < G; ++u, at = advance(at, 1)) {
+        const int32_t s = at.s;
+        const int32_t g = at.r * kTileBlock + tid;
+        const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+        uint32_t act = 0;  // bit j: bond j of the group is occupied and inside the tile
+        uint32_t packed[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool on = ((o[u] >> (8 * j)) & 0xFFu) != 0;
+          const int32_t vt = slot_of(c4[j]);
+          if (on && vt < 0) leave |= 1u << (4 * u + j);
+          act |= (uint32_t)(on && vt >= 0) << j;
+          const uint32_t ut = ((uint32_t)s << kGridTwShift) | (uint32_t)row_bond_site(4 * g + j, magic16);
+          packed[j] = (ut << 16) | ((uint32_t)vt & 0xFFFFu);
+        }
+        tile_join_compact(par, stage[wave], staged, act, packed);
+      }
+      uint32_t pslot = reserve_slots<kLeaveBits>(__popc(leave), &n_out);
+      if (leave) {  // static indices only: the register arrays must not spill
+        at = cur;
+#pragma unroll
+        for (int u = 0; u < G; ++u, at = advance(at, 1)) {
+          const int32_t s = at.s;
+          const int32_t g = at.r * kTileBlock + tid;
+          const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if ((leave >> (4 * u + j)) & 1u) {
+              const int64_t site = u0 + (int64_t)s * geo.w + row_bond_site(4 * g + j, magic16);
+              st_dev2(my_pairs + pslot++, make_int2((int32_t)site, c4[j]));
+            }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        c[u] = cn[u];
+        o[u] = on[u];
+      }
+      rv = rvn;
+      cur = advance(cur, G);
+    }
+    ok = rp_ok(iters, rv) && ok;  // requested by the last step
+    for (int32_t vs = iters + 1; vs < n_vslots; ++vs) ok = rp_ok(vs, rp_load(vs)) && ok;
+    if (tid < rows) {  // the end entry of each row (the last site's bond range)
+      const int32_t rel = tid * w32 + row_len(tid);
+      ok = buf_i32(rp, 4u * (uint32_t)rel) == (int32_t)((uint32_t)e_first + (uint32_t)deg * (uint32_t)rel) && ok;
+    }
+    if (staged > 0) join_batch(par, stage[wave], 0, staged);  // what is left on the stack
+    affine = __syncthreads_and(ok) != 0;
+    if (!affine) {
+      init_par();
+      __syncthreads();
+    }
+  }
+  if (!affine) {
+    // ---- rows: one tile row per pass, kRowsPerThread... here one site per
+    // lane and row (kTileBlock lanes x 4 = one 4096-site row), every bond of
+    // a site in turn, read with plain loads
+    for (int32_t s = 0; s < rows; ++s) {
+      const int32_t len = seg_len(s);
+      const int64_t us = u0 + (int64_t)s * geo.w;
+#pragma unroll
+      for (int k = 0; k < kGridTw / kTileBlock; ++k) {
+        const int32_t cc = k * kTileBlock + tid;
+        if (cc >= len) continue;
+        const int64_t u = us + cc;
+        const int32_t ut = (s << kGridTwShift) | cc;
+        const int32_t b0 = row_ptr[u], b1 = row_ptr[u + 1];
+        for (int32_t e = b0; e < b1; ++e) {
+          if ((HAS_OCC && occ[e] == 0) || (DRAW && !philox_occupied(rng, (uint64_t)e))) continue;
+          const int32_t v = col[e];
+          const int32_t vt = slot_of(v);
+          if (vt >= 0) {
+            lds16_unite(par, ut, vt);
+          } else {
+            const uint32_t sl =
+                __hip_atomic_fetch_add(&n_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            st_dev2(my_pairs + sl, make_int2((int32_t)u, v));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // the tile's labels: each site's tile-local root, two rows per pass, four
+  // sites of each per lane (a 4096-site row is one site group per lane),
+  // eight chases resolved together; 16-byte stores when the label array and
+  // the row length allow it
+  const bool vec = ((reinterpret_cast<uintptr_t>(label + u0) & 15) == 0) && (geo.w % 4 == 0);
+  const __amdgpu_buffer_rsrc_t rl = make_rsrc(label + u0, vec && fast ? (uint32_t)span_sites * 4u : 0u);
+  auto gid = [&](int32_t t) {
+    return (int32_t)(u0 + (int64_t)(t >> kGridTwShift) * geo.w + (t & (kGridTw - 1)));
+  };
+  const int32_t cc = 4 * tid;
+  for (int32_t s0 = 0; s0 < rows; s0 += 2) {
+    int32_t x[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t s = min(s0 + h, rows - 1);  // a missing second row repeats the first
+      const uint2 wv = reinterpret_cast<const uint2*>(par)[((s << kGridTwShift) | cc) >> 2];
+      x[4 * h + 0] = (int32_t)(wv.x & 0xFFFFu);
+      x[4 * h + 1] = (int32_t)(wv.x >> 16);
+      x[4 * h + 2] = (int32_t)(wv.y & 0xFFFFu);
+      x[4 * h + 3] = (int32_t)(wv.y >> 16);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t p = lds16_ld(par + x[k]);
+      if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t s = s0 + h;
+      const int32_t len = row_len(s);  // 0 past the last row
+      if (cc >= len) continue;
+      if (vec && fast && cc + 4 <= len) {
+        st_dev4(rl, 4u * (uint32_t)(s * w32 + cc),
+                make_int4(gid(x[4 * h]), gid(x[4 * h + 1]), gid(x[4 * h + 2]), gid(x[4 * h + 3])));
+      } else {
+        const int64_t us = u0 + (int64_t)s * geo.w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (cc + k < len) st_dev(label + us + cc + k, gid(x[4 * h + k]));
+      }
+    }
+  }
+  if (tid == 0) st_dev2(seg + blockIdx.x, make_int2((int32_t)region, (int32_t)n_out));
+}
+
 // Cross kernel: one workgroup per tile (tiles renumbered so that each XCD
 // takes a contiguous range of them and its L2 holds the neighbouring tiles
 // those joins touch) walks the tile's leaving-bond pairs in chunks.  Before
@@ -643,35 +1037,83 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, i
   for (int32_t t = 4 * cnt4 + tid; t < cnt; t += kFlatBlock) label[w0 + t] = w[t];
 }
 
-size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds) {
-  if (n_sites <= kCsrTile) return 0;
-  const int64_t n_tiles = (n_sites + kCsrTile - 1) / kCsrTile;
-  const size_t seg = ((size_t)n_tiles * sizeof(int2) + 255) & ~(size_t)255;
-  return seg + (size_t)n_bonds * sizeof(int2);
+// Tiles of the id grid of row length w: grid tiles when the rows are longer
+// than a grid tile, w is a multiple of 4 and there are at least kGridTh rows,
+// else slabs of kCsrTile consecutive ids (w <= 0: no grid).
+static bool use_grid(int64_t n, int64_t w) {
+  // w a multiple of 4 keeps every tile row's bonds on the same 4-byte
+  // alignment of the occupancy mask as the tile's first bond
+  return w > kGridTw && w < n && w % 4 == 0 && (n + w - 1) / w >= kGridTh;
 }
 
-ccl_status launch_label_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+static int64_t csr_tiles(int64_t n, int64_t w) {
+  if (!use_grid(n, w)) return (n + kCsrTile - 1) / kCsrTile;
+  const int64_t h = (n + w - 1) / w;
+  return ((h + kGridTh - 1) / kGridTh) * ((w + kGridTw - 1) / kGridTw);
+}
+
+// The tile table is sized for any grid width: with at least kGridTh rows of
+// more than kGridTw sites, ceil(h/16) ceil(w/4096) <= 4 ceil(n/65536) + 2.
+static size_t csr_seg_bytes(int64_t n_sites) {
+  const int64_t max_tiles = 4 * ((n_sites + kCsrTile - 1) / kCsrTile) + 2;
+  return ((size_t)max_tiles * sizeof(int2) + 255) & ~(size_t)255;
+}
+
+size_t csr_workspace_bytes(int64_t n_sites, int64_t n_bonds) {
+  if (n_sites <= kCsrTile) return 0;
+  return csr_seg_bytes(n_sites) + (size_t)n_bonds * sizeof(int2);
+}
+
+ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, const int32_t* col,
                             const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
                             void* workspace, hipStream_t s, const DeviceInfo& d) {
   if (n == 0) return CCL_OK;
-  const int64_t n_tiles = (n + kCsrTile - 1) / kCsrTile;
+  const bool grid = use_grid(n, grid_w);
+  const int64_t n_tiles = csr_tiles(n, grid_w);
+  if (n_tiles > 4 * ((n + kCsrTile - 1) / kCsrTile) + 2) return CCL_ERR_INVALID_VALUE;  // cannot happen
   int2* seg = nullptr;
   int2* pairs = nullptr;
   if (n_tiles > 1) {  // a single tile has no leaving bonds and needs no workspace
     seg = static_cast<int2*>(workspace);
-    pairs = reinterpret_cast<int2*>(static_cast<char*>(workspace) +
-                                    (((size_t)n_tiles * sizeof(int2) + 255) & ~(size_t)255));
+    pairs = reinterpret_cast<int2*>(static_cast<char*>(workspace) + csr_seg_bytes(n));
   }
   const PhiloxOcc rng = draw != nullptr ? *draw : PhiloxOcc{0, 0, 0};
-  if (occ != nullptr)
+  if (grid) {
+    GridGeo geo;
+    geo.n = n;
+    geo.w = grid_w;
+    geo.h = (n + grid_w - 1) / grid_w;
+    geo.tiles_x = (int32_t)((grid_w + kGridTw - 1) / kGridTw);
+    geo.inv_w = 1.0f / (float)grid_w;
+    geo.w_shift = 0;
+    while (((int64_t)1 << geo.w_shift) < grid_w) ++geo.w_shift;
+    const bool pow2 = ((int64_t)1 << geo.w_shift) == grid_w;
+#define CCL_GRID_TILE(OCC)                                                                      \
+  do {                                                                                          \
+    if (pow2)                                                                                   \
+      CCL_LAUNCH("ccl_csr_tile", (k_csr_tile_grid<OCC, true>), (unsigned)n_tiles, kTileBlock, 0, s, \
+                 geo, row_ptr, col, occ, label, pairs, seg, rng);                               \
+    else                                                                                        \
+      CCL_LAUNCH("ccl_csr_tile", (k_csr_tile_grid<OCC, false>), (unsigned)n_tiles, kTileBlock, 0, s, \
+                 geo, row_ptr, col, occ, label, pairs, seg, rng);                               \
+  } while (0)
+    if (occ != nullptr)
+      CCL_GRID_TILE(kOccMask);
+    else if (draw != nullptr)
+      CCL_GRID_TILE(kOccDraw);
+    else
+      CCL_GRID_TILE(kOccAll);
+#undef CCL_GRID_TILE
+  } else if (occ != nullptr) {
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccMask>, (unsigned)n_tiles, kTileBlock, 0, s, n,
                row_ptr, col, occ, label, pairs, seg, rng);
-  else if (draw != nullptr)
+  } else if (draw != nullptr) {
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccDraw>, (unsigned)n_tiles, kTileBlock, 0, s, n,
                row_ptr, col, occ, label, pairs, seg, rng);
-  else
+  } else {
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccAll>, (unsigned)n_tiles, kTileBlock, 0, s, n,
                row_ptr, col, occ, label, pairs, seg, rng);
+  }
   if (n_tiles == 1) return CCL_OK;
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)(n_tiles * kCrossSplit), kCrossBlock, 0, s, pairs, seg,
              label);

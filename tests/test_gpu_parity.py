@@ -41,9 +41,9 @@ def gpu_edges(ccl, n, src, dst, occ=None):
     return out.cpu().numpy()
 
 
-def gpu_csr(ccl, row_ptr, col, occ=None):
-    _say(f"ccl_label_csr n={len(row_ptr) - 1} m={len(col)}")
-    out = ccl.label_csr(dev(row_ptr), dev(col), None if occ is None else dev(occ))
+def gpu_csr(ccl, row_ptr, col, occ=None, grid_width=0):
+    _say(f"ccl_label_csr n={len(row_ptr) - 1} m={len(col)} grid_width={grid_width}")
+    out = ccl.label_csr(dev(row_ptr), dev(col), None if occ is None else dev(occ), grid_width=grid_width)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -168,11 +168,74 @@ def test_triangle_csr_multi_tile(ccl, L, p):
 
 @pytest.mark.parametrize("p", [0.3473, 0.1736, 0.5209])
 def test_config2_triangle_l8192_csr(ccl, p):
-    """Full size: triangle L=8192 periodic (67,108,864 sites), half-CSR."""
+    """Full size: triangle L=8192 periodic (67,108,864 sites), half-CSR, with
+    slab tiles and with grid tiles (grid width 8192, the configuration the
+    benchmark times)."""
     g = gen.triangle_csr_realization(8192, p, 2)
-    got = gpu_csr(ccl, g.row_ptr, g.col, g.occ)
     want = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
-    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(gpu_csr(ccl, g.row_ptr, g.col, g.occ), want)
+    np.testing.assert_array_equal(gpu_csr(ccl, g.row_ptr, g.col, g.occ, grid_width=8192), want)
+
+
+def rect_triangle_csr(w, h, n=None):
+    """Half-CSR of a w x h periodic triangular lattice (site y*w + x, forward
+    bonds to (x+1, y), (x, y+1), (x+1, y+1)); with n < w*h only the first n
+    sites, bonds to the missing ones dropped (non-affine rows at the end)."""
+    y, x = np.divmod(np.arange(w * h, dtype=np.int64), w)
+    nb = np.stack([y * w + (x + 1) % w, ((y + 1) % h) * w + x, ((y + 1) % h) * w + (x + 1) % w], 1)
+    n = w * h if n is None else n
+    nb = nb[:n]
+    keep = nb < n
+    deg = keep.sum(1)
+    row_ptr = np.zeros(n + 1, np.int32)
+    np.cumsum(deg, out=row_ptr[1:])
+    return row_ptr, nb[keep].astype(np.int32)
+
+
+@pytest.mark.parametrize("w,h,cut", [(8192, 40, 0), (8192, 40, 8192 - 100), (6004, 33, 0), (6004, 33, 5),
+                                     (12288, 20, 0), (4100, 17, 4100), (4104, 48, 0)])
+def test_csr_grid_tiles(ccl, w, h, cut):
+    """Grid tiles (16 rows x 4096 columns) on rectangular lattices: ragged
+    tile columns (w not a multiple of 4096) and tile rows (h not a multiple of
+    16), a partial last grid row whose missing sites make the last rows
+    non-affine (the row path), a tile with no site, no mask, a device-drawn
+    mask, and an occupancy view one byte off 4-byte alignment."""
+    n = w * h - cut
+    row_ptr, col = rect_triangle_csr(w, h, n)
+    occ = gen.bernoulli(w + h, len(col), 0.3473)
+    want = oracle.label_csr(n, row_ptr, col, occ)
+    np.testing.assert_array_equal(gpu_csr(ccl, row_ptr, col, occ, grid_width=w), want)
+    np.testing.assert_array_equal(gpu_csr(ccl, row_ptr, col, None, grid_width=w),
+                                  oracle.label_csr(n, row_ptr, col, None))
+    _say(f"grid tiles w={w} h={h} cut={cut}: drawn occupancy and an unaligned mask view")
+    out = ccl.label_csr_philox(dev(row_ptr), dev(col), w + h, gen.STREAM_OCC, 0.3473, grid_width=w)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+    buf = torch.zeros(len(occ) + 1, dtype=torch.uint8, device="cuda")
+    buf[1:] = dev(occ)
+    out = ccl.label_csr(dev(row_ptr), dev(col), buf[1:], grid_width=w)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
+def test_csr_grid_any_graph(ccl):
+    """The grid width changes only the tiling: ragged degrees and random
+    columns (never affine) give the oracle's labels for any width."""
+    rng = np.random.default_rng(12)
+    n = 300_000
+    deg = rng.integers(0, 7, n)
+    rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    c = rng.integers(0, n, rp[-1]).astype(np.int32)
+    o = (rng.random(rp[-1]) < 0.25).astype(np.uint8)
+    want = oracle.label_csr(n, rp, c, o)
+    for w in (4100, 8192, 10000, 15000):
+        np.testing.assert_array_equal(gpu_csr(ccl, rp, c, o, grid_width=w), want)
+    # a lattice numbered row by row, labelled with a wrong width
+    row_ptr, col = rect_triangle_csr(8192, 24)
+    occ = gen.bernoulli(9, len(col), 0.5)
+    want = oracle.label_csr(8192 * 24, row_ptr, col, occ)
+    for w in (4104, 8200, 12288):
+        np.testing.assert_array_equal(gpu_csr(ccl, row_ptr, col, occ, grid_width=w), want)
 
 
 def test_csr_forms(ccl):
