@@ -477,45 +477,101 @@ def bench_monte_carlo(L, p, seed, steps, warmup):
                            "labels_equal_mask_path": bool(torch.equal(sep, out))}}
 
 
-def bench_rspan_full(samples):
-    """R_span(p) of section 4 at the largest size class of Figs. 5-6 (triangle
-    L = 4096: 2^24 sites; honeycomb L = 2048: 2^23 sites), cylinders with open
-    top and bottom, occupancy drawn on the device, labelled on the GPU."""
+def crossing(ps, ra, rb, sa, sb):
+    """The p where two R_span curves on the same p grid cross (linear
+    interpolation of their difference at its sign change nearest the middle
+    of the grid) and its standard error from the binomial errors of the two
+    bracketing points."""
+    import numpy as np
+    d = np.asarray(rb) - np.asarray(ra)
+    sig = np.sqrt(np.asarray(ra) * (1 - np.asarray(ra)) / sa + np.asarray(rb) * (1 - np.asarray(rb)) / sb)
+    idx = [i for i in range(len(ps) - 1) if d[i] < 0 <= d[i + 1] or d[i] > 0 >= d[i + 1]]
+    if not idx:
+        return None, None
+    mid = len(ps) // 2
+    i = min(idx, key=lambda j: abs(j - mid))
+    slope = (d[i + 1] - d[i]) / (ps[i + 1] - ps[i])
+    if slope == 0:
+        return None, None
+    pc = ps[i] - d[i] / slope
+    err = float(max(sig[i], sig[i + 1]) / abs(slope))
+    return float(pc), err
+
+
+def bench_rspan_crossing(samples, sizes=None):
+    """Section 4, Figs. 5-6: R_span(p) on cylinders (open top and bottom,
+    periodic sides) of four sizes per lattice, occupancy drawn on the device,
+    labelled on the GPU (triangle: CSR with grid tiles; honeycomb: edge list),
+    spanning tested on the device; p_c estimated where the curves of
+    successive sizes cross, beside the paper's estimate and the exact
+    value."""
+    import math
     import numpy as np
     import torch
     import gen
     import paper_1603_08357_amd as ccl
+    exact = {"triangle": 2 * math.sin(math.pi / 18), "honeycomb": 1 - 2 * math.sin(math.pi / 18)}
+    paper = {"triangle": (0.3472, 0.0002), "honeycomb": (0.6527, 0.0002)}
+    sizes = sizes or {"triangle": (512, 1024, 2048, 4096), "honeycomb": (256, 512, 1024, 2048)}
+    offs = (-0.008, -0.006, -0.004, -0.003, -0.002, -0.001, -0.0005, 0.0, 0.0005, 0.001, 0.002, 0.003,
+            0.004, 0.006, 0.008)
     res = {}
-    for kind, L, pc in (("triangle", 4096, 0.3473), ("honeycomb", 2048, 0.6527)):
-        if kind == "triangle":
-            src, dst = gen.triangle_edges(L)
-            n, wrap = L * L, gen.y_wrap_bonds_triangle(L)
-            row = np.arange(n) // L
-        else:
-            src, dst = gen.honeycomb_edges(L)
-            n, wrap = 2 * L * L, gen.y_wrap_bonds_honeycomb(L)
-            row = (np.arange(n) // 2) // L
-        ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
-        dwrap = torch.from_numpy(np.nonzero(wrap)[0]).cuda()
-        top = torch.from_numpy(np.nonzero(row == 0)[0].astype(np.int32)).cuda()
-        bot = torch.from_numpy(np.nonzero(row == L - 1)[0].astype(np.int32)).cuda()
-        occ = torch.empty(len(src), dtype=torch.uint8, device="cuda")
-        lab = torch.empty(n, dtype=torch.int32, device="cuda")
-        curve = {}
+    for kind in ("triangle", "honeycomb"):
+        pc0 = round(exact[kind], 4)
+        ps = [round(pc0 + o, 5) for o in offs]
+        curves = {}
         t0 = time.perf_counter()
-        for dp in (-0.004, -0.002, 0.0, 0.002, 0.004):
-            p = round(pc + dp, 4)
-            hits = 0
-            for r in range(samples):
-                ccl.bernoulli(gen.mix_seed(9000 + r, int(p * 1e4)), gen.STREAM_OCC, len(src), p, out=occ)
-                occ.index_fill_(0, dwrap, 0)
-                ccl.label(ds, dd, n, occ, out=lab)
-                hits += int(ccl.spans(lab, top, bot).item())
-            curve[str(p)] = round(hits / samples, 4)
-        res[f"{kind}_L{L}"] = {"n_sites": n, "samples_per_p": samples, "R_span": curve,
-                               "seconds": round(time.perf_counter() - t0, 2)}
-        del ds, dd, occ, lab
-        torch.cuda.empty_cache()
+        for L in sizes[kind]:
+            if kind == "triangle":
+                row_ptr, col = gen.triangle_csr(L)
+                n, wrap = L * L, gen.y_wrap_bonds_triangle(L)
+                row = np.arange(n) // L
+                a, b = torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda()
+                m = len(col)
+            else:
+                src, dst = gen.honeycomb_edges(L)
+                n, wrap = 2 * L * L, gen.y_wrap_bonds_honeycomb(L)
+                row = (np.arange(n) // 2) // L
+                a, b = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+                m = len(src)
+            dwrap = torch.from_numpy(np.nonzero(wrap)[0]).cuda()
+            top = torch.from_numpy(np.nonzero(row == 0)[0].astype(np.int32)).cuda()
+            bot = torch.from_numpy(np.nonzero(row == L - 1)[0].astype(np.int32)).cuda()
+            occ = torch.empty(m, dtype=torch.uint8, device="cuda")
+            lab = torch.empty(n, dtype=torch.int32, device="cuda")
+            ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
+            hits = torch.zeros(len(ps), dtype=torch.int32, device="cuda")
+            for i, p in enumerate(ps):
+                for r in range(samples):
+                    ccl.bernoulli(gen.mix_seed(7000 + 97 * L + r, int(round(p * 1e5))), gen.STREAM_OCC, m, p,
+                                  out=occ)
+                    occ.index_fill_(0, dwrap, 0)
+                    if kind == "triangle":
+                        ccl.label_csr(a, b, occ, out=lab, workspace=ws, grid_width=L)
+                    else:
+                        ccl.label(a, b, n, occ, out=lab)
+                    hits[i:i + 1] += ccl.spans(lab, top, bot)
+            curves[L] = (hits.cpu().numpy() / samples).tolist()
+            log(f"R_span {kind} L={L}: {time.perf_counter() - t0:.1f}s")
+            del a, b, occ, lab, ws
+            torch.cuda.empty_cache()
+        Ls = list(sizes[kind])
+        xs = []
+        for L1, L2 in zip(Ls, Ls[1:]):
+            pc, err = crossing(ps, curves[L1], curves[L2], samples, samples)
+            xs.append({"sizes": [L1, L2], "p_cross": None if pc is None else round(pc, 5),
+                       "stderr": None if err is None else round(err, 5)})
+        good = [x for x in xs if x["p_cross"] is not None]
+        est = float(np.mean([x["p_cross"] for x in good])) if good else None
+        res[kind] = {"p": ps, "samples_per_point": samples,
+                     "n_sites": {str(L): (L * L if kind == "triangle" else 2 * L * L) for L in Ls},
+                     "R_span": {str(L): [round(v, 4) for v in curves[L]] for L in Ls},
+                     "crossings": xs,
+                     "p_c_estimate": None if est is None else round(est, 5),
+                     "p_c_spread": round(float(np.std([x["p_cross"] for x in good])), 5) if len(good) > 1 else None,
+                     "p_c_exact": round(exact[kind], 6),
+                     "p_c_paper": {"value": paper[kind][0], "error": paper[kind][1]},
+                     "seconds": round(time.perf_counter() - t0, 1)}
     return res
 
 
@@ -767,6 +823,8 @@ def main():
                     help="also run the 1 GiB copy probe (counter calibration) when --extras none")
     ap.add_argument("--pool", type=int, default=24, help="graphs in the serving pool")
     ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
+    ap.add_argument("--rspan-samples", type=int, default=1000,
+                    help="realizations per (size, p) point of the spanning-probability curves")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="store measured traffic from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -857,9 +915,9 @@ def main():
         except Exception as e:
             extra["monte_carlo"] = f"failed: {type(e).__name__}: {e}"
         try:
-            extra["R_span_full_size"] = bench_rspan_full(64)
+            extra["R_span_crossing"] = bench_rspan_crossing(args.rspan_samples)
         except Exception as e:
-            extra["R_span_full_size"] = f"failed: {type(e).__name__}: {e}"
+            extra["R_span_crossing"] = f"failed: {type(e).__name__}: {e}"
         try:
             extra["cluster_statistics"] = bench_stats(out, args.steps)
         except Exception as e:

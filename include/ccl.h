@@ -327,6 +327,21 @@ ccl_status ccl_cluster_sizes(int64_t n_sites, const int32_t* labels, int32_t* si
                              void* stream);
 
 /*
+ * The cluster-size distribution n_s of the percolation application (section
+ * 4): hist_out[s] = number of clusters of exactly s sites for 1 <= s <
+ * n_bins - 1, hist_out[n_bins - 1] = number of clusters of n_bins - 1 sites
+ * or more, hist_out[0] = 0.
+ *   sizes      device int32[N]: cluster sizes at the cluster minima, zero
+ *              elsewhere, as ccl_cluster_sizes writes them (entries <= 0 are
+ *              skipped)
+ *   n_bins     >= 2
+ *   hist_out   device int64[n_bins], 8-byte aligned, overwritten
+ * sum_s s * hist_out[s] = N when every bin is below n_bins - 1.
+ */
+ccl_status ccl_cluster_size_histogram(int64_t n_sites, const int32_t* sizes, int64_t n_bins,
+                                      int64_t* hist_out, void* stream);
+
+/*
  * The spanning test of section 4: *result_out = 1 when one cluster holds a
  * site of sites_a and a site of sites_b (e.g. the first and the last row of a
  * lattice), else 0.

@@ -19,8 +19,9 @@ probability p (section 4).
   and (ii) on its neighbour list, in numpy, for the paper's statement that
   standard numbering of the Bethe lattice leaves no residual list (so steps
   (i) and (ii) alone give the final labels).
-* ``cluster_sizes`` / ``sizes_by_minimum`` / ``cluster_ids`` / ``spans`` /
-  ``mean_cluster_size`` / ``largest_fraction``: percolation observables
+* ``cluster_sizes`` / ``sizes_by_minimum`` / ``size_histogram`` /
+  ``cluster_ids`` / ``spans`` / ``mean_cluster_size`` / ``largest_fraction``:
+  percolation observables
   (section 4) and the sequential renumbering (section 3) computed from a
   labeling with numpy.
 """
@@ -196,6 +197,17 @@ def sizes_by_minimum(labels: np.ndarray) -> np.ndarray:
     """sizes[r] = number of sites labelled r: each cluster's size at its
     minimum site, zero elsewhere."""
     return np.bincount(np.asarray(labels, np.int64), minlength=len(labels)).astype(np.int32)
+
+
+def size_histogram(labels: np.ndarray, n_bins: int) -> np.ndarray:
+    """n_s, the number of clusters of exactly s sites (the cluster-size
+    distribution of percolation theory, section 4's application): hist[s]
+    for 1 <= s < n_bins - 1, the last bin counting every cluster of
+    n_bins - 1 sites or more, hist[0] = 0.  Written from its definition:
+    count the sites of each cluster, then count the clusters of each size."""
+    sites_per_label = np.bincount(np.asarray(labels, np.int64))
+    sizes = sites_per_label[sites_per_label > 0]  # one entry per cluster
+    return np.bincount(np.minimum(sizes, n_bins - 1), minlength=n_bins).astype(np.int64)
 
 
 def cluster_ids(labels: np.ndarray):

@@ -18,7 +18,8 @@ import torch  # first: the library then binds to the HIP runtime torch loaded
 
 __all__ = [
     "CclError", "label", "label_philox", "label_csr", "label_csr_philox", "label_ell", "csr_workspace_bytes",
-    "philox_u32", "bernoulli", "cluster_ids", "cluster_ids_noalloc", "cluster_sizes", "spans", "Plan",
+    "philox_u32", "bernoulli", "cluster_ids", "cluster_ids_noalloc", "cluster_sizes", "size_histogram",
+    "spans", "Plan",
     "Tuning",
     "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
     "library_path", "version",
@@ -77,6 +78,7 @@ def _load():
         "ccl_cluster_ids_noalloc_max_sites": (sz, []),
         "ccl_cluster_ids_noalloc": (st, [i64, P, P, P, P]),
         "ccl_cluster_sizes": (st, [i64, P, P, P]),
+        "ccl_cluster_size_histogram": (st, [i64, P, i64, P, P]),
         "ccl_spans": (st, [i64, P, i64, P, i64, P, P, P, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
         "ccl_plan_destroy": (st, [P]),
@@ -265,6 +267,22 @@ def cluster_sizes(labels: torch.Tensor, out: torch.Tensor | None = None, stream=
     po = _dev_ptr(out, torch.int32, "out", n, dev)
     with torch.cuda.device(dev):
         _check(_lib.ccl_cluster_sizes(n, pl, po, _stream(stream, dev)), "ccl_cluster_sizes")
+    return out
+
+
+def size_histogram(sizes: torch.Tensor, n_bins: int, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """n_s from cluster_sizes' output: out[s] = number of clusters of s sites
+    (int64; the last bin holds every cluster of n_bins - 1 sites or more)."""
+    dev = sizes.device
+    n = sizes.numel()
+    ps = _dev_ptr(sizes, torch.int32, "sizes", None, dev)
+    if out is None:
+        out = torch.empty(n_bins, dtype=torch.int64, device=dev)
+    po = _dev_ptr(out, torch.int64, "out", n_bins, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.ccl_cluster_size_histogram(n, ps, n_bins, po, _stream(stream, dev)),
+               "ccl_cluster_size_histogram")
     return out
 
 

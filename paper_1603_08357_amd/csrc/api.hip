@@ -306,6 +306,19 @@ ccl_status ccl_cluster_sizes(int64_t n_sites, const int32_t* labels, int32_t* si
   return launch_cluster_sizes(n_sites, labels, sizes_out, (hipStream_t)stream, *d);
 }
 
+ccl_status ccl_cluster_size_histogram(int64_t n_sites, const int32_t* sizes, int64_t n_bins,
+                                      int64_t* hist_out, void* stream) {
+  if (n_sites < 0 || n_sites > INT32_MAX || n_bins < 2 || hist_out == nullptr)
+    return CCL_ERR_INVALID_VALUE;
+  if (n_sites > 0 && sizes == nullptr) return CCL_ERR_INVALID_VALUE;
+  if (((uintptr_t)hist_out & 7) != 0) return CCL_ERR_INVALID_VALUE;
+  if (overlaps(hist_out, (size_t)n_bins * 8, sizes, (size_t)n_sites * 4)) return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  return launch_size_histogram(n_sites, sizes, n_bins, hist_out, (hipStream_t)stream, *d);
+}
+
 ccl_status ccl_spans(int64_t n_sites, const int32_t* labels, int64_t n_a, const int32_t* sites_a,
                      int64_t n_b, const int32_t* sites_b, uint8_t* flags, int32_t* result_out,
                      void* stream) {

@@ -121,6 +121,8 @@ ccl_status launch_cluster_ids(int64_t n, const int32_t* label, int32_t* ids, int
                               void* workspace, hipStream_t s, const DeviceInfo& d);
 ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes, hipStream_t s,
                                 const DeviceInfo& d);
+ccl_status launch_size_histogram(int64_t n, const int32_t* sizes, int64_t n_bins, int64_t* hist,
+                                 hipStream_t s, const DeviceInfo& d);
 ccl_status launch_spans(int64_t n, const int32_t* label, int64_t n_a, const int32_t* a, int64_t n_b,
                         const int32_t* b, uint8_t* flags, int32_t* result, hipStream_t s,
                         const DeviceInfo& d);

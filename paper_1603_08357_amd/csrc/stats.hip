@@ -283,6 +283,69 @@ ccl_status launch_cluster_sizes(int64_t n, const int32_t* label, int32_t* sizes,
   return CCL_OK;
 }
 
+// ---------------------------------------------------------------- size histogram
+
+// n_s, the number of clusters of s sites, from the sizes at the cluster
+// minima (zero elsewhere): hist[min(s, n_bins - 1)] += 1 for every s > 0.
+// Each workgroup counts the bins below kHistLds in LDS and adds them to the
+// global histogram with one 64-bit atomic per nonzero bin; larger sizes (rare
+// at any p: few clusters are that large) go straight to global atomics.  The
+// histogram is cleared by a kernel, so the sequence can be captured in a graph.
+constexpr int kHistBlock = 1024;
+constexpr int kHistLds = 8192;
+
+__global__ void __launch_bounds__(256) k_hist_clear(int64_t n_bins, unsigned long long* hist) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_bins; i += stride)
+    __hip_atomic_store(hist + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kHistBlock)
+    k_hist_count(int64_t n, const int32_t* __restrict__ sizes, int64_t n_bins,
+                 unsigned long long* hist, bool vec) {
+  __shared__ uint32_t cnt[kHistLds];
+  const int64_t lds_bins = min((int64_t)kHistLds, n_bins);
+  for (int t = threadIdx.x; t < lds_bins; t += kHistBlock) cnt[t] = 0;
+  __syncthreads();
+  auto add = [&](int32_t sz) {
+    if (sz <= 0) return;
+    const int64_t b = min((int64_t)sz, n_bins - 1);
+    if (b < lds_bins)
+      __hip_atomic_fetch_add(&cnt[b], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      atomicAdd(hist + b, 1ull);
+  };
+  const int64_t stride = (int64_t)gridDim.x * kHistBlock;
+  const int64_t tid = (int64_t)blockIdx.x * kHistBlock + threadIdx.x;
+  int64_t done = 0;
+  if (vec) {
+    const int64_t n4 = n >> 2;
+    for (int64_t q = tid; q < n4; q += stride) {
+      const int4 v = reinterpret_cast<const int4*>(sizes)[q];
+      add(v.x);
+      add(v.y);
+      add(v.z);
+      add(v.w);
+    }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + tid; i < n; i += stride) add(sizes[i]);
+  __syncthreads();
+  for (int t = threadIdx.x; t < lds_bins; t += kHistBlock)
+    if (cnt[t]) atomicAdd(hist + t, (unsigned long long)cnt[t]);
+}
+
+ccl_status launch_size_histogram(int64_t n, const int32_t* sizes, int64_t n_bins, int64_t* hist,
+                                 hipStream_t s, const DeviceInfo& d) {
+  unsigned long long* h = reinterpret_cast<unsigned long long*>(hist);
+  CCL_LAUNCH("ccl_hist_clear", k_hist_clear, grid_for(n_bins, 256, 4, d), 256, 0, s, n_bins, h);
+  if (n == 0) return CCL_OK;
+  const bool vec = (reinterpret_cast<uintptr_t>(sizes) & 15) == 0;
+  CCL_LAUNCH("ccl_hist_count", k_hist_count, grid_for(vec ? (n + 3) / 4 : n, kHistBlock, 1, d), kHistBlock,
+             0, s, n, sizes, n_bins, h, vec);
+  return CCL_OK;
+}
+
 // ---------------------------------------------------------------- spanning
 
 // flags[label[a]] = 1 for every site a of A; then any site b of B whose

@@ -902,3 +902,28 @@ def test_concurrent_streams_match_oracle(ccl):
         if kind == "batched":
             for plan in ws:
                 plan.close()
+
+
+@pytest.mark.parametrize("L,p", [(512, 0.3473), (700, 0.5209), (8192, 0.3473)])
+def test_cluster_size_histogram(ccl, L, p):
+    """n_s on the GPU (ccl_cluster_sizes then ccl_cluster_size_histogram)
+    equals the oracle's histogram element by element: bins held in LDS,
+    bins past the LDS range (global atomics), a last bin that collects every
+    larger cluster, and a sizes view that is not 16-byte aligned."""
+    g = gen.triangle_csr_realization(L, p, 90 + L)
+    lab = oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)
+    dl = dev(lab)
+    sizes = ccl.cluster_sizes(dl)
+    for n_bins in (2, 3, 100, 9000, g.n_sites + 1):
+        _say(f"size histogram L={L} p={p} bins={n_bins}")
+        got = ccl.size_histogram(sizes, n_bins)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.size_histogram(lab, n_bins))
+    buf = torch.zeros(g.n_sites + 1, dtype=torch.int32, device="cuda")
+    buf[1:] = sizes
+    got = ccl.size_histogram(buf[1:], 50)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), oracle.size_histogram(lab, 50))
+    empty = ccl.size_histogram(torch.zeros(0, dtype=torch.int32, device="cuda"), 4)
+    torch.cuda.synchronize()
+    assert empty.cpu().tolist() == [0, 0, 0, 0]

@@ -125,3 +125,50 @@ def test_unmutated_ell_init_passes_the_pins():
 def test_pins_reject_ell_init_mutant(name):
     kw = ELL_MUTANTS[name]
     assert _ell_pins_reject(lambda n, z, nn, o: _ell_init_mutant(n, z, nn, o, **kw)), name
+
+
+# ---- the cluster-size histogram
+
+def _hist_mutant(labels, n_bins, *, count_sites=False, size_off_by_one=False, no_overflow_bin=False):
+    """oracle.size_histogram's definition with one planted error: sites
+    counted instead of clusters, sizes shifted by one, or clusters larger
+    than the last bin dropped instead of counted there."""
+    vals, counts = np.unique(np.asarray(labels, np.int64), return_counts=True)
+    hist = np.zeros(n_bins, np.int64)
+    for s in counts:
+        s = int(s) + (1 if size_off_by_one else 0)
+        if s >= n_bins and no_overflow_bin:
+            continue
+        hist[min(s, n_bins - 1)] += s if count_sites else 1
+    return hist
+
+
+HIST_MUTANTS = {
+    "counts sites instead of clusters": dict(count_sites=True),
+    "shifts every size by one": dict(size_off_by_one=True),
+    "drops clusters past the last bin": dict(no_overflow_bin=True),
+}
+
+
+def _hist_pins_reject(fn) -> bool:
+    import test_statistics as ts
+    for test in (ts.test_size_histogram_hand_worked, ts.test_size_histogram_sums_and_extremes):
+        saved = oracle.size_histogram
+        oracle.size_histogram = fn
+        try:
+            test()
+        except AssertionError:
+            return True
+        finally:
+            oracle.size_histogram = saved
+    return False
+
+
+def test_unmutated_histogram_passes_the_pins():
+    assert not _hist_pins_reject(lambda lab, nb: _hist_mutant(lab, nb))
+
+
+@pytest.mark.parametrize("name", sorted(HIST_MUTANTS))
+def test_pins_reject_histogram_mutant(name):
+    kw = HIST_MUTANTS[name]
+    assert _hist_pins_reject(lambda lab, nb: _hist_mutant(lab, nb, **kw)), name

@@ -133,3 +133,44 @@ def test_bethe_mean_cluster_size_other_z(z, p):
     want = (1 + p) / (1 - (z - 1) * p)
     got = np.mean([oracle.mean_cluster_size(_bethe_labels(1 << 19, z, p, 400 + s)) for s in range(6)])
     assert got == pytest.approx(want, rel=0.03)
+
+
+# ------------------------------------------------------------ cluster-size histogram
+
+def test_size_histogram_hand_worked():
+    # clusters {0,1}, {2,3,4}, {5}: one each of sizes 2, 3 and 1
+    lab = np.array([0, 0, 2, 2, 2, 5], np.int32)
+    assert oracle.size_histogram(lab, 8).tolist() == [0, 1, 1, 1, 0, 0, 0, 0]
+    # the last bin takes every cluster at least that large
+    assert oracle.size_histogram(lab, 3).tolist() == [0, 1, 2]
+
+
+def test_size_histogram_sums_and_extremes():
+    g = gen.triangle_realization(64, 0.35, 7)
+    lab = oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)
+    h = oracle.size_histogram(lab, g.n_sites + 1)
+    assert int((np.arange(len(h)) * h).sum()) == g.n_sites      # every site in one cluster
+    assert int(h.sum()) == len(np.unique(lab))                 # every cluster counted once
+    n = 1000
+    ident = np.arange(n, dtype=np.int32)                       # no bond occupied
+    assert oracle.size_histogram(ident, 5).tolist() == [0, n, 0, 0, 0]
+    whole = np.zeros(n, np.int32)                              # one cluster of every site
+    h = oracle.size_histogram(whole, n + 1)
+    assert h[n] == 1 and h.sum() == 1
+    assert oracle.size_histogram(whole, 10).tolist() == [0] * 9 + [1]
+
+
+def test_size_histogram_one_dimensional_closed_form():
+    """Bond percolation on an open chain of N sites: a cluster of s sites is
+    a run of s - 1 occupied bonds between two empty ones, so the expected
+    number of s-site clusters is about N (1 - p)^2 p^(s - 1) (textbook 1-D
+    percolation); a chain of 2,000,000 sites at p = 0.5 matches it to 1%."""
+    n, p = 2_000_000, 0.5
+    src = np.arange(n - 1, dtype=np.int32)
+    dst = src + 1
+    occ = gen.bernoulli(31, n - 1, p)
+    lab = oracle.label_edges(n, src, dst, occ)
+    h = oracle.size_histogram(lab, 12)
+    for s in range(1, 8):
+        want = n * (1 - p) ** 2 * p ** (s - 1)
+        assert abs(h[s] - want) / want < 0.01 + 4 / math.sqrt(want), (s, h[s], want)
