@@ -34,6 +34,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "labelled sites/s (Gsites/s) + % HBM peak; batched vs per-launch; p99 latency"
 
 
+# groups of extra measurements (--extras all runs them in this order)
+EXTRA_GROUPS = ["probes", "slab", "fig7", "honeycomb", "batched", "serving", "monte_carlo", "rspan", "stats",
+                "ell", "random3reg"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -275,7 +280,8 @@ def bench_edges(g, steps, warmup, cold=False):
     fn = lambda: ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
     ms, wall = time_steps(fn, steps, warmup, stream)
     kern = traced_kernels(fn, steps)
-    res = dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern)
+    res = dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern,
+               n_clusters=int((out == torch.arange(g.n_sites, dtype=torch.int32, device="cuda")).sum().item()))
     if cold:  # warm: back to back; cold: a 1 GiB write ahead of every step
         res["warm_step_ms"] = step_distribution(fn, steps, stream)
         res["cold_step_ms"] = step_distribution(fn, steps, stream, before=make_flush())
@@ -591,6 +597,49 @@ def probe_copy(nbytes=1 << 30):
     return {"bytes": 2 * nbytes, "ms": ms, "GBs": round(2 * nbytes / ms / 1e6, 1)}
 
 
+def probe_random_access(table_len=1 << 24, n_ops=1 << 27):
+    """Ceilings of scattered 4-byte accesses on a table the size of the random
+    graphs' label array (2^24 int32 = 64 MiB): independent loads, device-scope
+    atomicMin with the result discarded and used, and dependent-load chains
+    (time per step of one chain, with the chip full of chains)."""
+    import torch
+    import paper_1603_08357_amd as ccl
+    table = torch.zeros(table_len, dtype=torch.int32, device="cuda")
+    out = {"table_int32": table_len, "ops": n_ops}
+    ccl.probe_random(table, 0, 4)  # hashed next-indices: the chase's table, gathered too
+    for mode, name in ((3, "chase"), (0, "gather"), (1, "atomic_min"), (2, "atomic_min_ret")):
+        ccl.probe_random(table, n_ops // 8, mode)  # warm-up
+        torch.cuda.synchronize()
+        with ccl.trace() as rec:
+            ccl.probe_random(table, n_ops, mode)
+            torch.cuda.synchronize()
+        ms = rec[-1][1]
+        out[name + "_Gops"] = round(n_ops / (ms * 1e-3) / 1e9, 2)
+    lanes = torch.cuda.get_device_properties(0).multi_processor_count * 8 * 256 * 4
+    out["chase_step_ns"] = round(lanes / (out["chase_Gops"] * 1e9) * 1e9, 1)
+    del table
+    return out
+
+
+def random_access_roofline(g, rb, ceil):
+    """The random graph's labeling against the random-access ceilings: at
+    least two scattered label reads per occupied bond (merge), one atomicMin
+    per join (N minus the number of clusters), and one scattered parent read
+    per site (flatten); their ideal time at the probed rates beside the
+    measured path."""
+    import numpy as np
+    occupied = int(np.count_nonzero(g.occ))
+    n = g.n_sites
+    joins = n - int(rb.get("n_clusters", 0)) if rb.get("n_clusters") else None
+    reads = 2 * occupied + n
+    t_reads = reads / (ceil["gather_Gops"] * 1e9)
+    t_atom = (joins or 0) / (ceil["atomic_min_ret_Gops"] * 1e9)
+    ideal_ms = (t_reads + t_atom) * 1e3
+    return {"bound": "random-access", "scattered_reads": reads, "joins": joins,
+            "ideal_ms": round(ideal_ms, 5), "measured_ms": round(rb["ms"], 5),
+            "frac": round(ideal_ms / rb["ms"], 4)}
+
+
 def upload_batch(specs, chunk=64):
     """Generate a batch instance by instance on the host (in chunks) and copy
     it into device arrays; host memory stays at one chunk."""
@@ -817,7 +866,8 @@ def main():
     ap.add_argument("--p", type=float, default=0.3473)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", choices=["all", "none"], default="all")
+    ap.add_argument("--extras", default="all",
+                    help="all, none, or a comma list of: " + ",".join(EXTRA_GROUPS))
     ap.add_argument("--batch", type=int, default=4096, help="instances in the batched workload")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run the 1 GiB copy probe (counter calibration) when --extras none")
@@ -875,12 +925,23 @@ def main():
 
     if args.extras == "none" and args.probe_copy:
         extra["probe_copy"] = probe_copy()
-    if args.extras == "all":
-        try:
-            extra["probe_copy"] = probe_copy()
-        except Exception as e:  # measurement aid only
-            extra["probe_copy"] = f"failed: {e}"
-        # the same labeling with slab tiles (65536 consecutive ids; ccl_label_csr)
+    groups = EXTRA_GROUPS if args.extras == "all" else ([] if args.extras == "none" else args.extras.split(","))
+    unknown = [g_ for g_ in groups if g_ not in EXTRA_GROUPS]
+    if unknown:
+        raise SystemExit(f"unknown --extras groups {unknown}; choose from {EXTRA_GROUPS}, all or none")
+
+    def run(name, fn):
+        if name in groups:
+            try:
+                fn()
+            except Exception as e:  # an extra never takes the headline line down
+                extra[name] = f"failed: {type(e).__name__}: {e}"
+
+    def do_probes():
+        extra["probe_copy"] = probe_copy()
+        extra["probe_random_access"] = probe_random_access()
+
+    def do_slab():  # the same labeling with slab tiles (65536 consecutive ids; ccl_label_csr)
         gs, outs, rs = bench_csr(args.L, args.p, args.seed, max(5, args.steps // 2), args.warmup)
         extra["slab_tiles"] = {"Gsites_s": round(rs["n"] / (rs["ms"] * 1e-3) / 1e9, 3),
                                "ms_per_step": round(rs["ms"], 5),
@@ -888,7 +949,9 @@ def main():
                                "labels_equal_grid_tiles": bool(torch.equal(outs, out))}
         del gs, outs
         torch.cuda.empty_cache()
-        for pp in (0.1736, 0.5209):  # 0.5 p_c and 1.5 p_c of the same lattice
+
+    def do_fig7():  # 0.5 p_c and 1.5 p_c of the same lattice
+        for pp in (0.1736, 0.5209):
             gp, outp, rp_ = bench_csr(args.L, pp, args.seed, max(5, args.steps // 2), args.warmup,
                                       grid_width=args.L)
             extra[f"triangle_L{args.L}_p{pp}"] = {
@@ -897,44 +960,28 @@ def main():
                 "kernels": {k: round(v["mean_ms"], 5) for k, v in rp_["kernels"].items()}}
             del gp, outp
             torch.cuda.empty_cache()
+
+    def do_honeycomb():
         h = gen.honeycomb_realization(256, 0.6527, 1)
         _, rh = bench_edges(h, max(args.steps, 50), args.warmup)
         extra["honeycomb_L256"] = {"Gsites_s": round(rh["n"] / (rh["ms"] * 1e-3) / 1e9, 3),
                                    "ms_per_step": round(rh["ms"], 5),
                                    "kernels": {k: round(v["mean_ms"], 5) for k, v in rh["kernels"].items()}}
-        try:
-            extra["batched_4096"] = bench_batched(args.batch, 4, max(3, args.steps // 4), 1)
-        except Exception as e:
-            extra["batched_4096"] = f"failed: {type(e).__name__}: {e}"
-        try:
-            extra["serving"] = bench_serving(args.pool, args.requests, 5)
-        except Exception as e:
-            extra["serving"] = f"failed: {type(e).__name__}: {e}"
-        try:
-            extra["monte_carlo"] = bench_monte_carlo_set(args.L, args.seed, args.steps, args.warmup)
-        except Exception as e:
-            extra["monte_carlo"] = f"failed: {type(e).__name__}: {e}"
-        try:
-            extra["R_span_crossing"] = bench_rspan_crossing(args.rspan_samples)
-        except Exception as e:
-            extra["R_span_crossing"] = f"failed: {type(e).__name__}: {e}"
-        try:
-            extra["cluster_statistics"] = bench_stats(out, args.steps)
-        except Exception as e:
-            extra["cluster_statistics"] = f"failed: {type(e).__name__}: {e}"
-        try:
-            extra["ell"] = bench_ell_set(args.steps, args.warmup)
-        except Exception as e:
-            extra["ell"] = f"failed: {type(e).__name__}: {e}"
+
+    def do_random3reg():
+        ceil = extra.get("probe_random_access")
+        if not isinstance(ceil, dict):
+            ceil = extra["probe_random_access"] = probe_random_access()
         for pp in (0.45, 0.5, 0.55):
             b = gen.bethe_random_regular(1 << 24, 3, pp, 3)
             _, rb = bench_edges(b, args.steps, args.warmup, cold=True)
             gbs = path_bytes_edges(rb["n"], rb["m"]) / (rb["ms"] * 1e-3) / 1e9
-            extra[f"random3reg_2^24_p{pp}"] = {
-                "Gsites_s": round(rb["n"] / (rb["ms"] * 1e-3) / 1e9, 3),
-                "ms_per_step": round(rb["ms"], 5), "path_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                "warm_step_ms": rb["warm_step_ms"], "cold_step_ms": rb["cold_step_ms"],
-                "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()}}
+            row = {"Gsites_s": round(rb["n"] / (rb["ms"] * 1e-3) / 1e9, 3),
+                   "ms_per_step": round(rb["ms"], 5), "path_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "warm_step_ms": rb["warm_step_ms"], "cold_step_ms": rb["cold_step_ms"],
+                   "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()},
+                   "random_access_roofline": random_access_roofline(b, rb, ceil)}
+            extra[f"random3reg_2^24_p{pp}"] = row
             if pp == 0.5:
                 try:
                     extra["monte_carlo_random3reg_2^24_p0.5"] = bench_edges_monte_carlo(
@@ -942,6 +989,19 @@ def main():
                 except Exception as e:
                     extra["monte_carlo_random3reg_2^24_p0.5"] = f"failed: {type(e).__name__}: {e}"
             del b
+
+    run("probes", do_probes)
+    run("slab", do_slab)
+    run("fig7", do_fig7)
+    run("honeycomb", do_honeycomb)
+    run("batched", lambda: extra.__setitem__("batched_4096", bench_batched(args.batch, 4, max(3, args.steps // 4), 1)))
+    run("serving", lambda: extra.__setitem__("serving", bench_serving(args.pool, args.requests, 5)))
+    run("monte_carlo", lambda: extra.__setitem__("monte_carlo",
+                                                 bench_monte_carlo_set(args.L, args.seed, args.steps, args.warmup)))
+    run("rspan", lambda: extra.__setitem__("R_span_crossing", bench_rspan_crossing(args.rspan_samples)))
+    run("stats", lambda: extra.__setitem__("cluster_statistics", bench_stats(out, args.steps)))
+    run("ell", lambda: extra.__setitem__("ell", bench_ell_set(args.steps, args.warmup)))
+    run("random3reg", do_random3reg)
 
     line = {
         "metric": METRIC,

@@ -400,6 +400,21 @@ ccl_status ccl_trace_get(int i, const char** kernel_name, float* ms);
  */
 ccl_status ccl_probe_copy(const void* in, void* out, size_t bytes, void* stream);
 
+/*
+ * Random-access probes, the ceilings of the random graphs' labeling (bound by
+ * scattered 4-byte accesses rather than by streaming bandwidth).  table:
+ * device int32[table_len]; n_ops operations at hashed addresses spread over
+ * the table, four independent ones in flight per lane:
+ *   mode 0: loads (gather);  1: device-scope atomicMin, result discarded;
+ *   2: atomicMin with its result used;  3: dependent loads, each lane
+ *   following table[x] chains (fill the table with mode 4 first);
+ *   4: fill the table with hashed next-indices for mode 3.
+ * sink: device int32 the kernel may write (keeps the loads live).  Time the
+ * launch with ccl_trace_*; rate = n_ops / time.
+ */
+ccl_status ccl_probe_random(int32_t* table, int64_t table_len, int64_t n_ops, int32_t mode,
+                            int32_t* sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ __all__ = [
     "philox_u32", "bernoulli", "cluster_ids", "cluster_ids_noalloc", "cluster_sizes", "size_histogram",
     "spans", "Plan",
     "Tuning",
-    "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy",
+    "label_batched_per_instance", "validate_edges", "validate_csr", "trace", "probe_copy", "probe_random",
     "library_path", "version",
 ]
 
@@ -96,6 +96,7 @@ def _load():
         "ccl_trace_get": (st, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                ctypes.POINTER(ctypes.c_float)]),
         "ccl_probe_copy": (st, [P, P, sz, P]),
+        "ccl_probe_random": (st, [P, i64, i64, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -497,3 +498,14 @@ def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
     assert dst.numel() * dst.element_size() >= nbytes
     _check(_lib.ccl_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                nbytes, _stream(stream, src.device)), "ccl_probe_copy")
+
+
+def probe_random(table: torch.Tensor, n_ops: int, mode: int, stream=None):
+    """ccl_probe_random on an int32 GPU table (mode 0 gather, 1 atomicMin
+    discarded, 2 atomicMin used, 3 dependent chase, 4 fill for mode 3)."""
+    pt = _dev_ptr(table, torch.int32, "table", None, table.device)
+    sink = torch.zeros(1, dtype=torch.int32, device=table.device)
+    with torch.cuda.device(table.device):
+        _check(_lib.ccl_probe_random(pt, table.numel(), int(n_ops), int(mode),
+                                     ctypes.c_void_p(sink.data_ptr()), _stream(stream, table.device)),
+               "ccl_probe_random")

@@ -131,6 +131,8 @@ ccl_status launch_validate_edges(int64_t n, int64_t m, const int32_t* src, const
 ccl_status launch_validate_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
                                int64_t n_col, unsigned long long* d_count, hipStream_t s,
                                const DeviceInfo& d);
+ccl_status launch_probe_random(int32_t* table, int64_t len, int64_t n_ops, int32_t mode, int32_t* sink,
+                               hipStream_t s, const DeviceInfo& d);
 ccl_status launch_probe_copy(const void* in, void* out, size_t bytes, hipStream_t s,
                              const DeviceInfo& d);
 
