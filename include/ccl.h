@@ -404,7 +404,7 @@ ccl_status ccl_probe_copy(const void* in, void* out, size_t bytes, void* stream)
  * Random-access probes, the ceilings of the random graphs' labeling (bound by
  * scattered 4-byte accesses rather than by streaming bandwidth).  table:
  * device int32[table_len]; n_ops operations at hashed addresses spread over
- * the table, four independent ones in flight per lane:
+ * the table, sixteen independent ones in flight per lane:
  *   mode 0: loads (gather);  1: device-scope atomicMin, result discarded;
  *   2: atomicMin with its result used;  3: dependent loads, each lane
  *   following table[x] chains (fill the table with mode 4 first);

@@ -9,7 +9,7 @@
 namespace ccl {
 
 constexpr int kProbeBlock = 256;
-constexpr int kProbeIlp = 4;  // independent operations a lane keeps in flight
+constexpr int kProbeIlp = 16;  // independent operations a lane keeps in flight
 
 __device__ __forceinline__ uint32_t probe_index(uint64_t i, uint64_t len) {
   const uint64_t h = (i + 0x632BE59BD9B4E019ull) * 0x9E3779B97F4A7C15ull;
