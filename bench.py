@@ -696,14 +696,14 @@ def check_all_instances(specs, site_off, bond_off, labels, chunk=64):
 
 # the autotuner's search space for the benchmark's batch (a subset of
 # autotune.DEFAULT_SPACE, so the search takes seconds; the result is cached)
-BENCH_TUNE_SPACE = {"schedule": (2, 1), "block_threads": (256, 512), "blocks_per_cu": (2, 4),
+BENCH_TUNE_SPACE = {"schedule": (3, 2), "block_threads": (256, 512), "blocks_per_cu": (2, 4),
                     "bonds_per_chunk": (65536, 262144), "sites_per_chunk": (32768,), "small_sites": (0,)}
 
 
 def bench_batched(n_inst, base_seed, steps, warmup, check=True):
     """4096-instance mixed honeycomb / triangle batch: the plan's persistent
     kernel with the tuning the autotuner picks (and the library's defaults of
-    both schedules beside it), captured in a graph and replayed, against one
+    each schedule beside it), captured in a graph and replayed, against one
     ccl_label call per instance on the same buffers."""
     import torch
     import gen
@@ -724,7 +724,7 @@ def bench_batched(n_inst, base_seed, steps, warmup, check=True):
                        "cache": autotune.cache_path()}
     log(f"autotuned batch tuning {tuned} in {res['autotune']['seconds']} s")
     for name, tuning in (("batched_tuned", tuned), ("batched_phased_default", dict(schedule=2)),
-                         ("batched_fused_default", dict(schedule=1))):
+                         ("batched_fused_default", dict(schedule=1)), ("batched_tiled_default", dict(schedule=3))):
         plan = ccl.Plan(site_off, bond_off, tuning)
         with torch.cuda.stream(stream):
             plan.label(src, dst, occ, out=out, stream=stream)

@@ -200,7 +200,18 @@ typedef struct {
   int32_t schedule;        /* 1 = fused: one persistent launch in which work
                               items wait for the items they depend on;
                               2 = phased: init, merge and flatten items as
-                              three launches (no waiting); 0 = default (2) */
+                              three launches (no waiting);
+                              3 = tiled: instances above small_sites are
+                              cut into 65536-site tiles, each joined in LDS
+                              by one workgroup from its range of the bond
+                              list (the first bond whose src reaches the
+                              tile's first site starts it; bonds listed in
+                              order of src keep a tile's bonds together,
+                              any order stays exact), then the bonds that
+                              leave a tile are joined in global memory and
+                              the labels of instances of several tiles are
+                              flattened; bonds_per_chunk is not used;
+                              0 = default (3) */
 } ccl_tuning;
 
 /*
@@ -237,7 +248,8 @@ ccl_status ccl_plan_check(ccl_plan plan, int32_t* error_host);
  * Label every instance of the plan's layout: a small kernel that resets the
  * plan's counters (no memset node, so the launches can be captured into a HIP
  * graph and replayed), then the persistent kernel -- one launch for the fused
- * schedule, three for the phased one.
+ * schedule, three for the phased one; the tiled schedule adds a launch that
+ * finds the tiles' bond ranges, the tile launch and the leaving-bond launch.
  *   src, dst   device int32[total bonds], instance-local ids
  *   occupied   device uint8[total bonds] or NULL
  *   labels_out device int32[total sites]

@@ -2,17 +2,20 @@
 
 For one batch layout (instance offsets) and its device buffers, time a grid of
 ``ccl_tuning`` candidates -- workgroup size, resident workgroups per CU, work
-item sizes, the LDS small-instance path and the fused / phased schedule --
+item sizes, the LDS small-instance path and the fused / phased / tiled
+schedule --
 keep only candidates whose labels equal a reference labeling (by default the
 one-launch-per-instance schedule) and whose plan reports no error, and
 return the fastest.  Results are cached in a JSON file keyed by the device
-name and a coarse description of the layout (instance count and size
-quantiles), so later runs on the same kind of batch skip the search.
+name, a coarse description of the layout (instance count and size
+quantiles) and the search space, so later runs on the same kind of batch
+skip the search.
 
 Cache file: $CCL_AUTOTUNE_CACHE, else ~/.cache/ccl_mi355x/autotune.json.
 """
 from __future__ import annotations
 
+import hashlib
 import itertools
 import json
 import os
@@ -24,7 +27,7 @@ import torch
 import paper_1603_08357_amd as ccl
 
 DEFAULT_SPACE = {
-    "schedule": (2, 1),
+    "schedule": (3, 2, 1),
     "block_threads": (256, 512, 1024),
     "blocks_per_cu": (2, 4, 8),
     "bonds_per_chunk": (16384, 65536, 262144),
@@ -68,6 +71,12 @@ def _store_cache(d: dict) -> None:
     os.replace(tmp, p)
 
 
+def space_key(space=None) -> str:
+    full = dict(DEFAULT_SPACE, **(space or {}))
+    text = json.dumps({k: list(v) for k, v in sorted(full.items())})
+    return hashlib.sha1(text.encode()).hexdigest()[:12]
+
+
 def candidates(space=None, limit=None):
     space = dict(DEFAULT_SPACE, **(space or {}))
     keys = sorted(space)
@@ -76,6 +85,9 @@ def candidates(space=None, limit=None):
         t = dict(zip(keys, vals))
         lds = (max(t["small_sites"], 0) + 1) // 2 * 4  # 16-bit parents; 0 = library default
         if lds * t["blocks_per_cu"] > 160 * 1024:
+            continue
+        # the tiled schedule has no merge items: one bonds_per_chunk suffices
+        if t["schedule"] == 3 and t["bonds_per_chunk"] != min(space["bonds_per_chunk"]):
             continue
         out.append(t)
     return out[:limit] if limit else out
@@ -104,7 +116,7 @@ def tune(site_off, bond_off, src, dst, occ, space=None, reps: int = 3, use_cache
     from the batched kernel).  A candidate whose plan reports an error, or
     whose labels differ, is never chosen."""
     dev_name = torch.cuda.get_device_name()
-    key = f"{dev_name}|{layout_key(site_off)}"
+    key = f"{dev_name}|{layout_key(site_off)}|{space_key(space)}"
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         return dict(cache[key]["tuning"])

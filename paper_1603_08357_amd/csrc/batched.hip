@@ -36,13 +36,15 @@
 #include <vector>
 
 #include "common.hpp"
+#include "mem.hpp"
+#include "tile.hpp"
 #include "uf.hpp"
 
 namespace ccl {
 
 enum : uint32_t { kItemSmall = 0, kItemInit = 1, kItemMerge = 2, kItemFlatten = 3 };
 constexpr int kLockstep = 4;  // bonds a lane carries through one lockstep join
-enum : int32_t { kScheduleDefault = 0, kScheduleFused = 1, kSchedulePhased = 2 };
+enum : int32_t { kScheduleDefault = 0, kScheduleFused = 1, kSchedulePhased = 2, kScheduleTiled = 3 };
 
 __host__ __device__ inline uint64_t pack_item(uint32_t inst, uint32_t kind, uint32_t chunk) {
   return ((uint64_t)inst << 32) | ((uint64_t)kind << 30) | chunk;
@@ -267,6 +269,206 @@ __global__ void k_batched(BatchArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- tiled schedule
+//
+// Schedule 3 ("tiled") gives every instance of more than small_sites sites
+// the CSR path's treatment on its edge list: tiles of kCsrTile consecutive
+// instance-local sites, one workgroup per tile joining the tile's bonds in LDS
+// (16-bit parents), writing the tile's labels (tile-local roots) and listing
+// the bonds that leave the tile; then one workgroup per tile joins its listed
+// bonds in global memory (Algorithm 1), and the flatten items finish the
+// instances of more than one tile.  A tile's bonds are the instance's bonds
+// [r_t, r_t+1) with r_0 = 0, r_T = m and r_t = the first bond whose src is at
+// least the tile's first site (a binary search, made non-decreasing over t),
+// so the ranges partition the bonds: when each instance lists its bonds in
+// order of src (as the lattice generators do) a tile's bonds are exactly those
+// of its sites; otherwise any bond whose ends are not both in its range's tile
+// is simply treated as leaving, and the labels are still exact.
+constexpr int kTilePairs = 4096;  // listed leaving bonds per tile; a tile with more re-reads its range
+constexpr int32_t kTilePiece = 1 << 28;  // bonds a tile reads through one buffer resource
+
+struct BatchTileArgs {
+  const int64_t* site_off;
+  const int64_t* bond_off;
+  const int4* items;     // (instance, tile, index of the tile's range start, 0)
+  const int4* tinst;     // per tiled instance: (instance, first item, tiles, first range index)
+  int64_t* ranges;       // per tiled instance: tiles + 1 range bounds, instance-local bond indices
+  int32_t* counts;       // per item: leaving bonds listed; -1: the list overflowed
+  int2* pairs;           // per item: kTilePairs (src, dst), instance-local
+  const int32_t* src;
+  const int32_t* dst;
+  const uint8_t* occ;
+  int32_t* label;
+};
+
+// First index b of src[0..m) with src[b] >= x (src sorted in the fast case;
+// any array gives some index in [0, m]).
+__device__ __forceinline__ int64_t lower_bound_src(const int32_t* src, int64_t m, int32_t x) {
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (src[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One wavefront per tiled instance: the tiles' range starts in parallel,
+// then made non-decreasing with a running maximum (carried across groups of
+// 64 tiles).
+__global__ void __launch_bounds__(64) k_batched_ranges(BatchTileArgs a) {
+  const int4 ti = a.tinst[blockIdx.x];
+  const int64_t b0 = a.bond_off[ti.x];
+  const int64_t m = a.bond_off[ti.x + 1] - b0;
+  const int32_t* src = a.src + b0;
+  const int lane = threadIdx.x;
+  int64_t* starts = a.ranges + ti.w;  // tiles + 1 bounds
+  int64_t carry = 0;
+  for (int32_t t0 = 0; t0 < ti.z; t0 += 64) {
+    const int32_t t = t0 + lane;
+    int64_t r = carry;
+    if (t < ti.z && t > 0) r = max(carry, lower_bound_src(src, m, t * kCsrTile));
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t o = __shfl_up(r, d, 64);
+      if (lane >= d) r = max(r, o);
+    }
+    if (t < ti.z) st_dev2(reinterpret_cast<int2*>(starts + t), make_int2((int32_t)(uint32_t)r, (int32_t)(r >> 32)));
+    carry = __shfl(r, 63, 64);
+  }
+  if (lane == 0) st_dev2(reinterpret_cast<int2*>(starts + ti.z), make_int2((int32_t)(uint32_t)m, (int32_t)(m >> 32)));
+}
+
+template <bool HAS_OCC>
+__global__ void __launch_bounds__(kTileBlock) k_batched_tile(BatchTileArgs a) {
+  __shared__ uint16_t par[kCsrTile];
+  __shared__ uint32_t stage[kTileBlock / 64][kStageCap];
+  __shared__ uint32_t n_out;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int4 it = a.items[blockIdx.x];
+  const int64_t s0 = a.site_off[it.x];
+  const int32_t n = (int32_t)(a.site_off[it.x + 1] - s0);
+  const int32_t lo = it.y * kCsrTile;
+  const int32_t cnt = min(kCsrTile, n - lo);
+  const int64_t b0 = a.bond_off[it.x];
+  const int64_t r0 = a.ranges[it.z], r1 = a.ranges[it.z + 1];
+  const int64_t nb = r1 - r0;
+  const int32_t* src = a.src + b0 + r0;
+  const int32_t* dst = a.dst + b0 + r0;
+  const uint8_t* occ = HAS_OCC ? a.occ + b0 + r0 : nullptr;
+  int2* my_pairs = a.pairs + (int64_t)blockIdx.x * kTilePairs;
+  int32_t* lab = a.label + s0;
+  for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {
+    const uint32_t t = 8u * (uint32_t)w;
+    reinterpret_cast<uint4*>(par)[w] =
+        make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16), (t + 6) | ((t + 7) << 16));
+  }
+  if (tid == 0) n_out = 0;
+  __syncthreads();
+  // bonds in groups of four per lane (buffer loads: an offset past the range
+  // reads 0, which the per-bond bound below masks), staged joins as in the
+  // CSR tile kernel, leaving occupied bonds listed; the range is read in
+  // pieces of at most 2^28 bonds, so byte offsets fit the 32-bit resources
+  const bool occ4 = ((reinterpret_cast<uintptr_t>(occ) & 3) == 0);
+  uint32_t staged = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kTilePiece) {
+    const int64_t pn = min((int64_t)kTilePiece, nb - c0);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + c0, (uint32_t)pn * 4u);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + c0, (uint32_t)pn * 4u);
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(HAS_OCC ? occ + c0 : nullptr, HAS_OCC ? (uint32_t)pn : 0u);
+    const int32_t groups = (int32_t)((pn + 3) >> 2);
+    for (int32_t g0 = 0; g0 < groups; g0 += kTileBlock) {
+      const int32_t g = g0 + tid;
+      // a load that reaches past the range's end is range-checked as a
+      // whole, so the one group that straddles the end loads word by word
+      const bool whole = 4 * (int64_t)g + 4 <= pn;
+      const uint32_t off = whole ? 4u * (uint32_t)g : kOffNone;
+      int4 u4 = buf_i32x4(rs, off * 4u);
+      int4 v4 = buf_i32x4(rd, off * 4u);
+      uint32_t o4 = 0x01010101u;
+      if (HAS_OCC) {
+        if (occ4) {
+          o4 = buf_u32(ro, off);
+        } else {
+          o4 = buf_u8(ro, off) | (buf_u8(ro, off + 1u) << 8) | (buf_u8(ro, off + 2u) << 16) | (buf_u8(ro, off + 3u) << 24);
+        }
+      }
+      if (!whole && g < groups) {
+        const uint32_t t0 = 4u * (uint32_t)g;
+        u4 = make_int4(buf_i32(rs, 4u * t0), buf_i32(rs, 4u * t0 + 4u), buf_i32(rs, 4u * t0 + 8u), buf_i32(rs, 4u * t0 + 12u));
+        v4 = make_int4(buf_i32(rd, 4u * t0), buf_i32(rd, 4u * t0 + 4u), buf_i32(rd, 4u * t0 + 8u), buf_i32(rd, 4u * t0 + 12u));
+        if (HAS_OCC)
+          o4 = buf_u8(ro, t0) | (buf_u8(ro, t0 + 1u) << 8) | (buf_u8(ro, t0 + 2u) << 16) | (buf_u8(ro, t0 + 3u) << 24);
+      }
+      const int32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+      const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+      uint32_t act = 0, leave = 0;
+      uint32_t packed[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool on = 4 * (int64_t)g + j < pn && ((o4 >> (8 * j)) & 0xFFu) != 0;
+        const uint32_t ul = (uint32_t)(u[j] - lo), vl = (uint32_t)(v[j] - lo);
+        const bool inside = ul < (uint32_t)cnt && vl < (uint32_t)cnt;
+        act |= (uint32_t)(on && inside) << j;
+        leave |= (uint32_t)(on && !inside && u[j] != v[j]) << j;
+        packed[j] = (ul << 16) | (vl & 0xFFFFu);
+      }
+      tile_join_compact(par, stage[wave], staged, act, packed);
+      uint32_t slot = reserve_slots<3>(__popc(leave), &n_out);
+      if (leave) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((leave >> j) & 1u) {
+            if (slot < (uint32_t)kTilePairs) st_dev2(my_pairs + slot, make_int2(u[j], v[j]));
+            ++slot;
+          }
+      }
+    }
+  }
+  if (staged > 0) join_batch(par, stage[wave], 0, staged);
+  __syncthreads();
+  // the tile's labels (instance-local): each site's tile-local root
+  for (int32_t t = tid; t < cnt; t += kTileBlock) st_dev(lab + lo + t, lo + lds16_find(par, t));
+  if (tid == 0)
+    st_dev(a.counts + blockIdx.x, n_out > (uint32_t)kTilePairs ? -1 : (int32_t)n_out);
+}
+
+// One workgroup per tile: the listed leaving bonds joined in global memory,
+// one per lane in lockstep; a tile whose list overflowed reads its bond range
+// again and joins every occupied bond that is not inside the tile.
+__global__ void __launch_bounds__(512) k_batched_cross(BatchTileArgs a) {
+  const int4 it = a.items[blockIdx.x];
+  const int64_t s0 = a.site_off[it.x];
+  const int32_t n = (int32_t)(a.site_off[it.x + 1] - s0);
+  const int32_t lo = it.y * kCsrTile;
+  const int32_t cnt = min(kCsrTile, n - lo);
+  int32_t* lab = a.label + s0;
+  const int32_t count = a.counts[blockIdx.x];
+  bool unused = false;
+  if (count >= 0) {
+    const int2* p = a.pairs + (int64_t)blockIdx.x * kTilePairs;
+    for (int32_t j0 = 0; j0 < count; j0 += 512) {
+      const int32_t j = j0 + threadIdx.x;
+      const int2 e = p[j < count ? j : 0];
+      int32_t x[1] = {j < count ? e.x : 0}, y[1] = {j < count ? e.y : 0};
+      unite_lockstep<1, 2, false>(lab, x, y, unused);
+    }
+    return;
+  }
+  // the list overflowed: the range is read again and every occupied bond
+  // that is not inside the tile (those were joined in LDS) is joined here
+  const int64_t b0 = a.bond_off[it.x];
+  const int64_t r0 = a.ranges[it.z], r1 = a.ranges[it.z + 1];
+  for (int64_t b = r0 + threadIdx.x; b < r1; b += 512) {
+    if (a.occ && a.occ[b0 + b] == 0) continue;
+    const int32_t u = a.src[b0 + b], v = a.dst[b0 + b];
+    if ((uint32_t)(u - lo) < (uint32_t)cnt && (uint32_t)(v - lo) < (uint32_t)cnt) continue;
+    unite(lab, u, v);
+  }
+}
+
 }  // namespace ccl
 
 // ---------------------------------------------------------------- plan
@@ -285,6 +487,14 @@ struct ccl_plan_s {
   uint64_t* d_items = nullptr;
   uint32_t* d_ctl = nullptr;  // [0..2] queue heads, [3] error word
   int32_t* d_done = nullptr;  // init_done[K], merge_done[K]
+  // tiled schedule
+  int64_t n_tiles = 0;        // tile items
+  int32_t n_tiled = 0;        // instances split into tiles
+  int4* d_tiles = nullptr;    // (instance, tile, range index, 0)
+  int4* d_tinst = nullptr;    // (instance, first tile item, tiles, first range index)
+  int64_t* d_ranges = nullptr;
+  int32_t* d_counts = nullptr;
+  int2* d_pairs = nullptr;
 };
 
 using namespace ccl;
@@ -304,7 +514,7 @@ static ccl_tuning resolve_tuning(const ccl_tuning* t, const DeviceInfo& d) {
     const int cap = (160 * 1024) / r.blocks_per_cu / 2 - 128;
     r.small_sites = std::min(cap, std::min(16384, d.max_lds_per_block / 2 - 128));
   }
-  if (r.schedule == kScheduleDefault) r.schedule = kSchedulePhased;
+  if (r.schedule == kScheduleDefault) r.schedule = kScheduleTiled;
   return r;
 }
 
@@ -319,7 +529,8 @@ static bool tuning_ok(const ccl_tuning& t, const DeviceInfo& d) {
   if (t.small_sites > 65536) return false;  // 16-bit LDS parents
   if (small_lds_bytes(t) + 64 > d.max_lds_per_block) return false;
   if ((small_lds_bytes(t) + 64) * t.blocks_per_cu > 160 * 1024) return false;
-  if (t.schedule != kScheduleFused && t.schedule != kSchedulePhased) return false;
+  if (t.schedule != kScheduleFused && t.schedule != kSchedulePhased && t.schedule != kScheduleTiled)
+    return false;
   return true;
 }
 
@@ -373,7 +584,24 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   };
   std::vector<uint64_t> items;
   int64_t phase_end[3] = {0, 0, 0};
-  if (t.schedule == kScheduleFused) {
+  std::vector<int4> tile_items, tiled;
+  int64_t n_ranges = 0;
+  if (t.schedule == kScheduleTiled) {
+    // phase 1: SMALL items (the tile items run in their own launch); phase 3:
+    // FLATTEN items of the instances of more than one tile
+    for (int32_t k : small) emit(items, k, kItemSmall, 1);
+    phase_end[0] = phase_end[1] = (int64_t)items.size();
+    for (int32_t k : large) {
+      const int64_t n = site_off_host[k + 1] - site_off_host[k];
+      const int32_t nt = (int32_t)((n + kCsrTile - 1) / kCsrTile);
+      tiled.push_back(make_int4(k, (int32_t)tile_items.size(), nt, (int32_t)n_ranges));
+      for (int32_t tt = 0; tt < nt; ++tt) tile_items.push_back(make_int4(k, tt, (int32_t)(n_ranges + tt), 0));
+      n_ranges += nt + 1;
+      if (nt > 1) emit(items, k, kItemFlatten, n_init(k));
+    }
+    phase_end[2] = (int64_t)items.size();
+    if ((int64_t)tile_items.size() >= INT32_MAX || n_ranges >= INT32_MAX) return CCL_ERR_INVALID_VALUE;
+  } else if (t.schedule == kScheduleFused) {
     const int64_t L = (int64_t)large.size();
     for (int64_t s = 0; s < L + 2; ++s) {
       if (s < L) emit(items, large[s], kItemInit, n_init(large[s]));
@@ -410,7 +638,11 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   const size_t item_bytes = sizeof(uint64_t) * items.size();
   const size_t ctl_bytes = 256 + sizeof(int32_t) * 2 * (size_t)n_inst;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = up(off_bytes) * 2 + up(item_bytes) + up(ctl_bytes);
+  const size_t nt = tile_items.size();
+  const size_t tile_bytes = up(sizeof(int4) * nt) + up(sizeof(int4) * tiled.size()) +
+                            up(sizeof(int64_t) * (size_t)n_ranges) + up(sizeof(int32_t) * nt) +
+                            sizeof(int2) * (size_t)kTilePairs * nt;
+  const size_t total = up(off_bytes) * 2 + up(item_bytes) + up(ctl_bytes) + tile_bytes;
   hipError_t e = hipMalloc(&p->dev_block, total);
   if (e != hipSuccess) {
     delete p;
@@ -422,11 +654,26 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
   p->d_items = reinterpret_cast<uint64_t*>(base + 2 * up(off_bytes));
   p->d_ctl = reinterpret_cast<uint32_t*>(base + 2 * up(off_bytes) + up(item_bytes));
   p->d_done = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(p->d_ctl) + 256);
+  char* tb = reinterpret_cast<char*>(p->d_ctl) + up(ctl_bytes);
+  p->n_tiles = (int64_t)nt;
+  p->n_tiled = (int32_t)tiled.size();
+  p->d_tiles = reinterpret_cast<int4*>(tb);
+  tb += up(sizeof(int4) * nt);
+  p->d_tinst = reinterpret_cast<int4*>(tb);
+  tb += up(sizeof(int4) * tiled.size());
+  p->d_ranges = reinterpret_cast<int64_t*>(tb);
+  tb += up(sizeof(int64_t) * (size_t)n_ranges);
+  p->d_counts = reinterpret_cast<int32_t*>(tb);
+  tb += up(sizeof(int32_t) * nt);
+  p->d_pairs = reinterpret_cast<int2*>(tb);
   e = hipMemcpy(p->d_site_off, site_off_host, off_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_bond_off, bond_off_host, off_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess && item_bytes)
     e = hipMemcpy(p->d_items, items.data(), item_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(p->d_ctl, 0, up(ctl_bytes));
+  if (e == hipSuccess && nt) e = hipMemcpy(p->d_tiles, tile_items.data(), sizeof(int4) * nt, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tiled.empty())
+    e = hipMemcpy(p->d_tinst, tiled.data(), sizeof(int4) * tiled.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(p->dev_block);
@@ -472,7 +719,7 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
   const DeviceInfo* d = current_device();
   if (!d) return CCL_ERR_HIP;
   if (d->device != plan->device) return CCL_ERR_INVALID_VALUE;
-  if (plan->n_items == 0) return CCL_OK;
+  if (plan->n_items == 0 && plan->n_tiles == 0) return CCL_OK;
   hipStream_t s = (hipStream_t)stream;
   const bool fused = plan->tuning.schedule == kScheduleFused;
   const int64_t n_done = fused ? 2 * (int64_t)plan->n_inst : 0;
@@ -501,15 +748,39 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
     return CCL_OK;
   }
   static const char* names[3] = {"ccl_batched_init", "ccl_batched_merge", "ccl_batched_flatten"};
+  BatchTileArgs ta;
+  ta.site_off = plan->d_site_off;
+  ta.bond_off = plan->d_bond_off;
+  ta.items = plan->d_tiles;
+  ta.tinst = plan->d_tinst;
+  ta.ranges = plan->d_ranges;
+  ta.counts = plan->d_counts;
+  ta.pairs = plan->d_pairs;
+  ta.src = src;
+  ta.dst = dst;
+  ta.occ = occupied;
+  ta.label = labels_out;
+  const bool tiled = plan->tuning.schedule == kScheduleTiled;
+  if (tiled && plan->n_tiled > 0)
+    CCL_LAUNCH("ccl_batched_ranges", k_batched_ranges, (unsigned)plan->n_tiled, 64, 0, s, ta);
   int64_t begin = 0;
   for (int ph = 0; ph < 3; ++ph) {
     a.items = plan->d_items + begin;
     a.n_items = plan->phase_end[ph] - begin;
     a.head = plan->d_ctl + ph;
     begin = plan->phase_end[ph];
-    if (a.n_items == 0) continue;
-    const unsigned g = (unsigned)std::min<int64_t>(plan->grid, a.n_items);
-    CCL_LAUNCH(names[ph], k_batched, g, plan->tuning.block_threads, ph == 0 ? lds : 0, s, a);
+    if (a.n_items > 0) {
+      const unsigned g = (unsigned)std::min<int64_t>(plan->grid, a.n_items);
+      CCL_LAUNCH(names[ph], k_batched, g, plan->tuning.block_threads, ph == 0 ? lds : 0, s, a);
+    }
+    if (tiled && plan->n_tiles > 0 && ph == 0) {
+      if (occupied)
+        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<true>, (unsigned)plan->n_tiles, kTileBlock, 0, s, ta);
+      else
+        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<false>, (unsigned)plan->n_tiles, kTileBlock, 0, s, ta);
+    }
+    if (tiled && plan->n_tiles > 0 && ph == 1)
+      CCL_LAUNCH("ccl_batched_cross", k_batched_cross, (unsigned)plan->n_tiles, 512, 0, s, ta);
   }
   return CCL_OK;
 }

@@ -574,7 +574,8 @@ BATCH_TUNINGS = [None, dict(schedule=2, small_sites=-1),
                  dict(schedule=2, block_threads=256, blocks_per_cu=2, bonds_per_chunk=4096,
                       sites_per_chunk=2048),
                  dict(schedule=1), dict(schedule=1, small_sites=-1, bonds_per_chunk=8192,
-                                        sites_per_chunk=4096)]
+                                        sites_per_chunk=4096),
+                 dict(schedule=3), dict(schedule=3, small_sites=-1, sites_per_chunk=4096)]
 
 
 @pytest.mark.parametrize("tuning", BATCH_TUNINGS, ids=lambda t: str(t))
@@ -619,7 +620,7 @@ def test_batched_with_empty_instances(ccl):
     np.testing.assert_array_equal(out.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_batched_graph_replay(ccl, schedule):
     """Capture the batched launch in a HIP graph, replay it several times with
     eager work in between, and check every replay."""
@@ -822,8 +823,8 @@ def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
     site_off, bond_off, src, dst, occ = _batch(specs)
     want = oracle.label_batched(site_off, bond_off, src, dst, occ)
     space = {"block_threads": (256, 512), "blocks_per_cu": (2, 4), "bonds_per_chunk": (16384,),
-             "sites_per_chunk": (16384,), "small_sites": (0, -1), "schedule": (2, 1)}
-    _say("autotune 16 candidates")
+             "sites_per_chunk": (16384,), "small_sites": (0, -1), "schedule": (3, 2, 1)}
+    _say("autotune 24 candidates")
     best = autotune.tune(site_off, bond_off, dev(src), dev(dst), dev(occ), space=space, reps=2)
     assert (tmp_path / "cache.json").exists()
     again = autotune.tune(site_off, bond_off, dev(src), dev(dst), dev(occ), space=space)
@@ -927,3 +928,41 @@ def test_cluster_size_histogram(ccl, L, p):
     empty = ccl.size_histogram(torch.zeros(0, dtype=torch.int32, device="cuda"), 4)
     torch.cuda.synchronize()
     assert empty.cpu().tolist() == [0, 0, 0, 0]
+
+
+
+@pytest.mark.parametrize("small_sites", [0, -1])
+def test_batched_tiled_any_bond_order(ccl, small_sites):
+    """The tiled schedule on instances whose bonds are not ordered by src
+    (shuffled lattices: a tile's range then holds bonds of other tiles, which
+    are joined as leaving bonds), random multigraphs with far more leaving
+    bonds than a tile's list holds (the range is read again), instances of one
+    tile, of several tiles and empty ones; every label equals the oracle's."""
+    rng = np.random.default_rng(77 + small_sites)
+    parts = []
+    for L in (100, 300, 400):
+        s_, d_ = gen.triangle_edges(L)
+        o_ = gen.bernoulli(L, len(s_), 0.45)
+        perm = rng.permutation(len(s_))
+        parts.append((L * L, s_[perm], d_[perm], o_[perm]))
+        parts.append((L * L, s_, d_, o_))
+    for n, m in ((150_001, 400_000), (70_000, 10), (5, 0), (0, 0)):
+        parts.append((n, rng.integers(0, max(n, 1), m).astype(np.int32), rng.integers(0, max(n, 1), m).astype(np.int32),
+                      (rng.random(m) < 0.5).astype(np.uint8)))
+    site_off = np.concatenate([[0], np.cumsum([p_[0] for p_ in parts])]).astype(np.int64)
+    bond_off = np.concatenate([[0], np.cumsum([len(p_[1]) for p_ in parts])]).astype(np.int64)
+    src = np.concatenate([p_[1] for p_ in parts]).astype(np.int32)
+    dst = np.concatenate([p_[2] for p_ in parts]).astype(np.int32)
+    occ = np.concatenate([p_[3] for p_ in parts]).astype(np.uint8)
+    want = oracle.label_batched(site_off, bond_off, src, dst, occ)
+    plan = ccl.Plan(site_off, bond_off, dict(schedule=3, small_sites=small_sites))
+    _say(f"tiled batch K={len(parts)} sites={site_off[-1]} small_sites={small_sites}")
+    for rep in range(2):
+        out = plan.label(dev(src), dev(dst), dev(occ))
+        torch.cuda.synchronize()
+        assert plan.check() == 0
+        np.testing.assert_array_equal(out.cpu().numpy(), want, err_msg=f"launch {rep}")
+    out = plan.label(dev(src), dev(dst), None)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), oracle.label_batched(site_off, bond_off, src, dst, None))
+    plan.close()

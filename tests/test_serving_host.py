@@ -153,7 +153,11 @@ def test_autotune_candidates_and_layout_key():
     c = autotune.candidates()
     assert len(c) > 20
     assert all((max(t["small_sites"], 0) + 1) // 2 * 4 * t["blocks_per_cu"] <= 160 * 1024 for t in c)
-    assert {t["schedule"] for t in c} == {1, 2}
+    assert {t["schedule"] for t in c} == {1, 2, 3}
+    # the tiled schedule has no merge items: one bonds_per_chunk only
+    assert len({t["bonds_per_chunk"] for t in c if t["schedule"] == 3}) == 1
+    assert autotune.space_key() != autotune.space_key({"schedule": (2,)})
+    assert autotune.space_key({"schedule": (3, 2, 1)}) == autotune.space_key()
     k1 = autotune.layout_key([0, 100, 300, 1300])
     k2 = autotune.layout_key([0, 110, 320, 1270])  # sizes 110, 210, 950
     assert k1 == k2 and k1.startswith("K3-")
