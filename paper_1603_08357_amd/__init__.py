@@ -48,6 +48,7 @@ class Tuning(ctypes.Structure):
 
     FUSED = 1
     PHASED = 2
+    TILED = 3
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

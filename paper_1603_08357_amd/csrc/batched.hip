@@ -272,7 +272,7 @@ __global__ void k_batched(BatchArgs a) {
 // ---------------------------------------------------------------- tiled schedule
 //
 // Schedule 3 ("tiled") gives every instance of more than small_sites sites
-// the CSR path's treatment on its edge list: tiles of kCsrTile consecutive
+// the CSR path's treatment on its edge list: tiles of 65536 consecutive
 // instance-local sites, one workgroup per tile joining the tile's bonds in LDS
 // (16-bit parents), writing the tile's labels (tile-local roots) and listing
 // the bonds that leave the tile; then one workgroup per tile joins its listed
@@ -286,6 +286,10 @@ __global__ void k_batched(BatchArgs a) {
 // is simply treated as leaving, and the labels are still exact.
 constexpr int kTilePairs = 4096;  // listed leaving bonds per tile; a tile with more re-reads its range
 constexpr int32_t kTilePiece = 1 << 28;  // bonds a tile reads through one buffer resource
+constexpr int kBatchGroups = 2;           // groups of four bonds per lane per step of the tile stream
+constexpr int32_t kBatchTile = kCsrTile;  // sites per tile (16-bit LDS parents)
+constexpr int kBatchBlock = kTileBlock;   // threads of a tile workgroup
+constexpr int kBatchTilesPerCu = 1;       // resident tile workgroups per compute unit
 
 struct BatchTileArgs {
   const int64_t* site_off;
@@ -329,7 +333,7 @@ __global__ void __launch_bounds__(64) k_batched_ranges(BatchTileArgs a) {
   for (int32_t t0 = 0; t0 < ti.z; t0 += 64) {
     const int32_t t = t0 + lane;
     int64_t r = carry;
-    if (t < ti.z && t > 0) r = max(carry, lower_bound_src(src, m, t * kCsrTile));
+    if (t < ti.z && t > 0) r = max(carry, lower_bound_src(src, m, t * kBatchTile));
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t o = __shfl_up(r, d, 64);
@@ -342,16 +346,16 @@ __global__ void __launch_bounds__(64) k_batched_ranges(BatchTileArgs a) {
 }
 
 template <bool HAS_OCC>
-__global__ void __launch_bounds__(kTileBlock) k_batched_tile(BatchTileArgs a) {
-  __shared__ uint16_t par[kCsrTile];
-  __shared__ uint32_t stage[kTileBlock / 64][kStageCap];
+__global__ void __launch_bounds__(kBatchBlock, kBatchTilesPerCu) k_batched_tile(BatchTileArgs a) {
+  __shared__ uint16_t par[kBatchTile];
+  __shared__ uint32_t stage[kBatchBlock / 64][kStageCap];
   __shared__ uint32_t n_out;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int4 it = a.items[blockIdx.x];
   const int64_t s0 = a.site_off[it.x];
   const int32_t n = (int32_t)(a.site_off[it.x + 1] - s0);
-  const int32_t lo = it.y * kCsrTile;
-  const int32_t cnt = min(kCsrTile, n - lo);
+  const int32_t lo = it.y * kBatchTile;
+  const int32_t cnt = min(kBatchTile, n - lo);
   const int64_t b0 = a.bond_off[it.x];
   const int64_t r0 = a.ranges[it.z], r1 = a.ranges[it.z + 1];
   const int64_t nb = r1 - r0;
@@ -360,7 +364,7 @@ __global__ void __launch_bounds__(kTileBlock) k_batched_tile(BatchTileArgs a) {
   const uint8_t* occ = HAS_OCC ? a.occ + b0 + r0 : nullptr;
   int2* my_pairs = a.pairs + (int64_t)blockIdx.x * kTilePairs;
   int32_t* lab = a.label + s0;
-  for (int w = tid; w < kCsrTile / 8; w += kTileBlock) {
+  for (int w = tid; w < kBatchTile / 8; w += kBatchBlock) {
     const uint32_t t = 8u * (uint32_t)w;
     reinterpret_cast<uint4*>(par)[w] =
         make_uint4(t | ((t + 1) << 16), (t + 2) | ((t + 3) << 16), (t + 4) | ((t + 5) << 16), (t + 6) | ((t + 7) << 16));
@@ -373,21 +377,24 @@ __global__ void __launch_bounds__(kTileBlock) k_batched_tile(BatchTileArgs a) {
   // pieces of at most 2^28 bonds, so byte offsets fit the 32-bit resources
   const bool occ4 = ((reinterpret_cast<uintptr_t>(occ) & 3) == 0);
   uint32_t staged = 0;
+  constexpr int G = kBatchGroups;
   for (int64_t c0 = 0; c0 < nb; c0 += kTilePiece) {
     const int64_t pn = min((int64_t)kTilePiece, nb - c0);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + c0, (uint32_t)pn * 4u);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + c0, (uint32_t)pn * 4u);
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(HAS_OCC ? occ + c0 : nullptr, HAS_OCC ? (uint32_t)pn : 0u);
     const int32_t groups = (int32_t)((pn + 3) >> 2);
-    for (int32_t g0 = 0; g0 < groups; g0 += kTileBlock) {
-      const int32_t g = g0 + tid;
-      // a load that reaches past the range's end is range-checked as a
-      // whole, so the one group that straddles the end loads word by word
+    const int32_t iters = (groups + G * kBatchBlock - 1) / (G * kBatchBlock);
+    // group g of step k, slot i: g = (G k + i) kBatchBlock + tid.  A load that
+    // reaches past the range's end is range-checked as a whole, so the one
+    // group that straddles the end loads word by word.
+    auto load = [&](int32_t k, int i, int4& u4, int4& v4, uint32_t& o4) {
+      const int32_t g = (G * k + i) * kBatchBlock + tid;
       const bool whole = 4 * (int64_t)g + 4 <= pn;
       const uint32_t off = whole ? 4u * (uint32_t)g : kOffNone;
-      int4 u4 = buf_i32x4(rs, off * 4u);
-      int4 v4 = buf_i32x4(rd, off * 4u);
-      uint32_t o4 = 0x01010101u;
+      u4 = buf_i32x4(rs, off * 4u);
+      v4 = buf_i32x4(rd, off * 4u);
+      o4 = 0x01010101u;
       if (HAS_OCC) {
         if (occ4) {
           o4 = buf_u32(ro, off);
@@ -402,35 +409,56 @@ __global__ void __launch_bounds__(kTileBlock) k_batched_tile(BatchTileArgs a) {
         if (HAS_OCC)
           o4 = buf_u8(ro, t0) | (buf_u8(ro, t0 + 1u) << 8) | (buf_u8(ro, t0 + 2u) << 16) | (buf_u8(ro, t0 + 3u) << 24);
       }
-      const int32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
-      const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
-      uint32_t act = 0, leave = 0;
-      uint32_t packed[4];
+    };
+    int4 cu[G], cv[G], nu[G], nv[G];
+    uint32_t co[G], no[G];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool on = 4 * (int64_t)g + j < pn && ((o4 >> (8 * j)) & 0xFFu) != 0;
-        const uint32_t ul = (uint32_t)(u[j] - lo), vl = (uint32_t)(v[j] - lo);
-        const bool inside = ul < (uint32_t)cnt && vl < (uint32_t)cnt;
-        act |= (uint32_t)(on && inside) << j;
-        leave |= (uint32_t)(on && !inside && u[j] != v[j]) << j;
-        packed[j] = (ul << 16) | (vl & 0xFFFFu);
+    for (int i = 0; i < G; ++i) load(0, i, cu[i], cv[i], co[i]);
+    for (int32_t k = 0; k < iters; ++k) {
+      // the next step's loads go out before this step's joins
+      if (k + 1 < iters) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) load(k + 1, i, nu[i], nv[i], no[i]);
       }
-      tile_join_compact(par, stage[wave], staged, act, packed);
-      uint32_t slot = reserve_slots<3>(__popc(leave), &n_out);
-      if (leave) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if ((leave >> j) & 1u) {
-            if (slot < (uint32_t)kTilePairs) st_dev2(my_pairs + slot, make_int2(u[j], v[j]));
-            ++slot;
-          }
+      for (int i = 0; i < G; ++i) {
+        const int32_t g = (G * k + i) * kBatchBlock + tid;
+        const int32_t u[4] = {cu[i].x, cu[i].y, cu[i].z, cu[i].w};
+        const int32_t v[4] = {cv[i].x, cv[i].y, cv[i].z, cv[i].w};
+        uint32_t act = 0, leave = 0;
+        uint32_t packed[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool on = 4 * (int64_t)g + j < pn && ((co[i] >> (8 * j)) & 0xFFu) != 0;
+          const uint32_t ul = (uint32_t)(u[j] - lo), vl = (uint32_t)(v[j] - lo);
+          const bool inside = ul < (uint32_t)cnt && vl < (uint32_t)cnt;
+          act |= (uint32_t)(on && inside) << j;
+          leave |= (uint32_t)(on && !inside && u[j] != v[j]) << j;
+          packed[j] = (ul << 16) | (vl & 0xFFFFu);
+        }
+        tile_join_compact(par, stage[wave], staged, act, packed);
+        uint32_t slot = reserve_slots<3>(__popc(leave), &n_out);
+        if (leave) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if ((leave >> j) & 1u) {
+              if (slot < (uint32_t)kTilePairs) st_dev2(my_pairs + slot, make_int2(u[j], v[j]));
+              ++slot;
+            }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        cu[i] = nu[i];
+        cv[i] = nv[i];
+        co[i] = no[i];
       }
     }
   }
-  if (staged > 0) join_batch(par, stage[wave], 0, staged);
+  drain_joins(par, stage[wave], staged);
   __syncthreads();
   // the tile's labels (instance-local): each site's tile-local root
-  for (int32_t t = tid; t < cnt; t += kTileBlock) st_dev(lab + lo + t, lo + lds16_find(par, t));
+  for (int32_t t = tid; t < cnt; t += kBatchBlock) st_dev(lab + lo + t, lo + lds16_find(par, t));
   if (tid == 0)
     st_dev(a.counts + blockIdx.x, n_out > (uint32_t)kTilePairs ? -1 : (int32_t)n_out);
 }
@@ -442,8 +470,8 @@ __global__ void __launch_bounds__(512) k_batched_cross(BatchTileArgs a) {
   const int4 it = a.items[blockIdx.x];
   const int64_t s0 = a.site_off[it.x];
   const int32_t n = (int32_t)(a.site_off[it.x + 1] - s0);
-  const int32_t lo = it.y * kCsrTile;
-  const int32_t cnt = min(kCsrTile, n - lo);
+  const int32_t lo = it.y * kBatchTile;
+  const int32_t cnt = min(kBatchTile, n - lo);
   int32_t* lab = a.label + s0;
   const int32_t count = a.counts[blockIdx.x];
   bool unused = false;
@@ -593,7 +621,7 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
     phase_end[0] = phase_end[1] = (int64_t)items.size();
     for (int32_t k : large) {
       const int64_t n = site_off_host[k + 1] - site_off_host[k];
-      const int32_t nt = (int32_t)((n + kCsrTile - 1) / kCsrTile);
+      const int32_t nt = (int32_t)((n + kBatchTile - 1) / kBatchTile);
       tiled.push_back(make_int4(k, (int32_t)tile_items.size(), nt, (int32_t)n_ranges));
       for (int32_t tt = 0; tt < nt; ++tt) tile_items.push_back(make_int4(k, tt, (int32_t)(n_ranges + tt), 0));
       n_ranges += nt + 1;
@@ -775,9 +803,9 @@ ccl_status ccl_label_batched(ccl_plan plan, const int32_t* src, const int32_t* d
     }
     if (tiled && plan->n_tiles > 0 && ph == 0) {
       if (occupied)
-        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<true>, (unsigned)plan->n_tiles, kTileBlock, 0, s, ta);
+        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<true>, (unsigned)plan->n_tiles, kBatchBlock, 0, s, ta);
       else
-        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<false>, (unsigned)plan->n_tiles, kTileBlock, 0, s, ta);
+        CCL_LAUNCH("ccl_batched_tile", k_batched_tile<false>, (unsigned)plan->n_tiles, kBatchBlock, 0, s, ta);
     }
     if (tiled && plan->n_tiles > 0 && ph == 1)
       CCL_LAUNCH("ccl_batched_cross", k_batched_cross, (unsigned)plan->n_tiles, 512, 0, s, ta);

@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(kTileBlock)
     for (int32_t g = iters * kTileBlock + tid; g < g4; g += kTileBlock) ok = rp_ok(g, rp_load(g)) && ok;
     for (int32_t t = 4 * g4 + tid; t < cnt; t += kTileBlock)
       ok = buf_i32(rp, 4u * (uint32_t)t) == e_begin + deg * t && ok;
-    if (staged > 0) join_batch(par, stage[wave], 0, staged);  // what is left on the stack
+    drain_joins(par, stage[wave], staged);  // what is left on the stack
     affine = __syncthreads_and(ok) != 0;
     if (!affine) {
       init_par();
@@ -646,7 +646,7 @@ __global__ void __launch_bounds__(kTileBlock)
       const int32_t rel = tid * w32 + row_len(tid);
       ok = buf_i32(rp, 4u * (uint32_t)rel) == (int32_t)((uint32_t)e_first + (uint32_t)deg * (uint32_t)rel) && ok;
     }
-    if (staged > 0) join_batch(par, stage[wave], 0, staged);  // what is left on the stack
+    drain_joins(par, stage[wave], staged);  // what is left on the stack
     affine = __syncthreads_and(ok) != 0;
     if (!affine) {
       init_par();
