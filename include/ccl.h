@@ -141,10 +141,10 @@ ccl_status ccl_label_csr(int64_t n_sites, int64_t n_bonds, const int32_t* row_pt
  * y*grid_width + x (a lattice of row length grid_width, as the paper's
  * lattices are numbered).  The result does not depend on grid_width -- any
  * CSR graph is labelled correctly with any value -- but the tiles follow the
- * grid: 16 rows of 4096 columns instead of 65536 consecutive ids, so a tile
+ * grid: 32 rows of 2048 columns instead of 65536 consecutive ids, so a tile
  * has a shorter boundary and fewer bonds leave it (on the 8192-wide
- * triangular lattice half as many).  Used when grid_width is a multiple of
- * 4, larger than 4096 and smaller than n_sites with at least 16 rows;
+ * triangular lattice a quarter as many).  Used when grid_width is a multiple
+ * of 4, larger than 2048 and smaller than n_sites with at least 32 rows;
  * otherwise (grid_width = 0 included) this is ccl_label_csr.  grid_width < 0:
  * CCL_ERR_INVALID_VALUE.  The other arguments, the workspace size and the
  * errors are ccl_label_csr's.

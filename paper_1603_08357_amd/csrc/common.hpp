@@ -106,7 +106,7 @@ struct PhiloxOcc;
 ccl_status launch_label_edges(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                               const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
                               hipStream_t s, const DeviceInfo& d);
-// grid_w: row length of the id grid (tiles of 16 rows x 4096 columns), or 0
+// grid_w: row length of the id grid (tiles of 32 rows x 2048 columns), or 0
 ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, const int32_t* col,
                             const uint8_t* occ, const PhiloxOcc* draw, int32_t* label,
                             void* workspace, hipStream_t s, const DeviceInfo& d);

@@ -43,8 +43,8 @@ __device__ __forceinline__ int32_t affine_row(int32_t e, uint32_t magic) {
 }
 
 // Site column of bond e of a tile row of degree d <= 4, as e * ceil(2^16 / d)
-// >> 16 with one 24-bit multiply: exact for e < 2^14 (a 4096-site row has at
-// most 16384 bonds); `magic16` is ceil(2^16 / d).
+// >> 16 with one 24-bit multiply: exact for e < 2^14 (a grid tile row of at
+// most 4096 sites has at most 16384 bonds); `magic16` is ceil(2^16 / d).
 __device__ __forceinline__ int32_t row_bond_site(int32_t e, uint32_t magic16) {
   return (int32_t)(__umul24((uint32_t)e, magic16) >> 16);
 }
@@ -352,22 +352,25 @@ __global__ void __launch_bounds__(kTileBlock)
 // of 65536/W rows whose two long edges cross up to 2W bonds each way: on the
 // 8192-wide triangular lattice a quarter of the sites sit on a slab edge and
 // the cross kernel gets 5.8 M leaving bonds at p_c.  A grid tile is instead
-// kGridTh rows of kGridTw columns (16 x 4096): half the edge per site, so
-// half the leaving bonds, and in the 16-row tiles the clusters are still
-// small enough for the LDS union to stay cheap (taller tiles cost more in
-// the tile kernel than they save in the cross kernel).  Any CSR graph is
+// kGridTh rows of kGridTw columns (32 x 2048): a quarter of the edge per
+// site, so a quarter of the leaving bonds.  Taller tiles hold larger
+// clusters, whose LDS joins cost more; on MI355X the 32 x 2048 tile was the
+// fastest whole path (tile kernel 0.518 ms, cross 0.082, flatten 0.173 on
+// the 8192^2 triangular lattice at p_c, against 0.469 / 0.145 / 0.187 for
+// 16 x 4096 and 0.560 / 0.056 / 0.162 for 64 x 1024).  Any CSR graph is
 // labelled correctly with any W; W only changes which bonds stay inside a
-// tile.  Tile (ty, tx) holds rows [16 ty, 16 ty + 16) and columns
-// [4096 tx, 4096 tx + cw); tile-relative slot t = (row << 12) | column, so
+// tile.  Tile (ty, tx) holds rows [32 ty, 32 ty + 32) and columns
+// [2048 tx, 2048 tx + cw); tile-relative slot t = (row << 11) | column, so
 // slot order is id order and the LDS roots are still the tile minima.
 // Tile-row ty's bonds form one contiguous range of the CSR, and tile tx of
-// that row takes the slots [start + bonds of columns < 4096 tx in each of its
+// that row takes the slots [start + bonds of columns < 2048 tx in each of its
 // rows, + its own bonds) of the pair list: the tiles' regions are disjoint
 // and exactly as large as their bond counts, for any CSR.
-constexpr int kGridTwShift = 12;
+constexpr int kGridTwShift = 11;
 constexpr int kGridTw = 1 << kGridTwShift;
 constexpr int kGridTh = kCsrTile / kGridTw;
 static_assert(kGridTh <= 64, "one lane per tile row in the header loads");
+static_assert(kGridTw >= kTileBlock && (4 * kTileBlock) % kGridTw == 0, "the epilogue's runs cover whole rows");
 
 struct GridGeo {
   int64_t n;        // sites
@@ -474,8 +477,8 @@ __global__ void __launch_bounds__(kTileBlock)
   // fields (below); otherwise a float quotient corrected by one step (exact:
   // the row index within reach is below kGridTh).
   // With w = 2^w_shift (>= 2 kGridTw), an id is (row, column) in bit fields,
-  // the tile is the ids whose bits above the low 12 of the column and above
-  // the low 4 of the row equal the tile's (mask pow2_m, pattern pow2_b), and
+  // the tile is the ids whose bits above the low 11 of the column and above
+  // the low 5 of the row equal the tile's (mask pow2_m, pattern pow2_b), and
   // the slot is those low bits side by side.
   const uint32_t pow2_m = POW2 ? ~((uint32_t)(kGridTw - 1) | ((uint32_t)(kGridTh - 1) << geo.w_shift)) : 0u;
   const uint32_t pow2_b = POW2 ? ((uint32_t)x0 | (uint32_t)(y0 << geo.w_shift)) : 0u;
@@ -654,9 +657,8 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   if (!affine) {
-    // ---- rows: one tile row per pass, kRowsPerThread... here one site per
-    // lane and row (kTileBlock lanes x 4 = one 4096-site row), every bond of
-    // a site in turn, read with plain loads
+    // ---- rows: one tile row per pass, kGridTw / kTileBlock sites per lane,
+    // every bond of a site in turn, read with plain loads
     for (int32_t s = 0; s < rows; ++s) {
       const int32_t len = seg_len(s);
       const int64_t us = u0 + (int64_t)s * geo.w;
@@ -683,22 +685,23 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   __syncthreads();
-  // the tile's labels: each site's tile-local root, two rows per pass, four
-  // sites of each per lane (a 4096-site row is one site group per lane),
-  // eight chases resolved together; 16-byte stores when the label array and
-  // the row length allow it
+  // the tile's labels: each site's tile-local root.  A pass takes two runs
+  // of 4 kTileBlock consecutive slots, four per lane (a run covers whole
+  // tile rows), eight chases resolved together; 16-byte stores when the
+  // label array and the row length allow it
   const bool vec = ((reinterpret_cast<uintptr_t>(label + u0) & 15) == 0) && (geo.w % 4 == 0);
   const __amdgpu_buffer_rsrc_t rl = make_rsrc(label + u0, vec && fast ? (uint32_t)span_sites * 4u : 0u);
   auto gid = [&](int32_t t) {
     return (int32_t)(u0 + (int64_t)(t >> kGridTwShift) * geo.w + (t & (kGridTw - 1)));
   };
-  const int32_t cc = 4 * tid;
-  for (int32_t s0 = 0; s0 < rows; s0 += 2) {
+  constexpr int32_t kRun = 4 * kTileBlock;  // slots per run
+  const int32_t n_runs = (rows * kGridTw + kRun - 1) / kRun;
+  for (int32_t q0 = 0; q0 < n_runs; q0 += 2) {
     int32_t x[8];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int32_t s = min(s0 + h, rows - 1);  // a missing second row repeats the first
-      const uint2 wv = reinterpret_cast<const uint2*>(par)[((s << kGridTwShift) | cc) >> 2];
+      const int32_t t = min(q0 + h, n_runs - 1) * kRun + 4 * tid;  // a missing second run repeats the first
+      const uint2 wv = reinterpret_cast<const uint2*>(par)[t >> 2];
       x[4 * h + 0] = (int32_t)(wv.x & 0xFFFFu);
       x[4 * h + 1] = (int32_t)(wv.x >> 16);
       x[4 * h + 2] = (int32_t)(wv.y & 0xFFFFu);
@@ -715,7 +718,9 @@ __global__ void __launch_bounds__(kTileBlock)
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int32_t s = s0 + h;
+      if (q0 + h >= n_runs) continue;
+      const int32_t t = (q0 + h) * kRun + 4 * tid;
+      const int32_t s = t >> kGridTwShift, cc = t & (kGridTw - 1);
       const int32_t len = row_len(s);  // 0 past the last row
       if (cc >= len) continue;
       if (vec && fast && cc + 4 <= len) {
@@ -984,7 +989,8 @@ static int64_t csr_tiles(int64_t n, int64_t w) {
 }
 
 // The tile table is sized for any grid width: with at least kGridTh rows of
-// more than kGridTw sites, ceil(h/16) ceil(w/4096) <= 4 ceil(n/65536) + 2.
+// more than kGridTw sites, ceil(h/kGridTh) ceil(w/kGridTw) <= 4 ceil(n/65536) + 2
+// (kGridTh kGridTw = 65536).
 static size_t csr_seg_bytes(int64_t n_sites) {
   const int64_t max_tiles = 4 * ((n_sites + kCsrTile - 1) / kCsrTile) + 2;
   return ((size_t)max_tiles * sizeof(int2) + 255) & ~(size_t)255;

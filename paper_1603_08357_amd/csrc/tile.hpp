@@ -37,43 +37,73 @@ constexpr int kLdsRounds = 4;  // lockstep pointer-following rounds in LDS befor
 // on critical lattices.  Each pair that goes back has a strictly smaller sum
 // of ends (parents are always below their children, and a displaced link's
 // parent is below the root it hung under), so the stack drains.
-constexpr int kJoinBatch = 64;
+constexpr int kJoinPer = 1;  // entries a lane joins per batch, their round trips shared
+constexpr int kJoinBatch = 64 * kJoinPer;
 constexpr int kStageCap = kJoinBatch - 1 + 256;  // leftover + one group of 64 x 4
 
-// Joins stage[base, limit) (limit - base <= 64), one entry per lane; pairs
-// that are not finished are written back from stage[base] on.  Returns how
-// many.
+// Joins stage[base, limit) (limit - base <= kJoinBatch), kJoinPer entries
+// per lane; pairs that are not finished are written back from stage[base]
+// on.  Returns how many.
 __device__ __forceinline__ uint32_t join_batch(uint16_t* par, uint32_t* stage, uint32_t base,
                                                uint32_t limit) {
+  constexpr int J = kJoinPer;
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t i = base + lane;
-  const uint32_t e = i < limit ? stage[i] : 0u;  // (0, 0): a no-op pair
-  int32_t a = (int32_t)(e >> 16), b = (int32_t)(e & 0xFFFFu);
-  int32_t pa = lds16_ld(par + a), pb = lds16_ld(par + b);
-  const int32_t ga = lds16_ld(par + pa), gb = lds16_ld(par + pb);
-  if (ga != pa) lds16_st(par + a, ga);  // halving: a now hangs under its grandparent
-  if (gb != pb) lds16_st(par + b, gb);
-  const bool roots = ga == pa && gb == pb;
-  const int32_t hi = max(pa, pb), lo = min(pa, pb);
-  const bool go = roots && hi != lo;
-  // the link: hi's 16-bit half of its word takes lo; a lane with nothing to
-  // link issues an empty mask on the word of its own end
-  const uint32_t sh = (uint32_t)(hi & 1) * 16u;
-  uint32_t ret[1];
-  const uint32_t off[1] = {(uint32_t)reinterpret_cast<uintptr_t>(par) + 4u * (uint32_t)(hi >> 1)};
-  const uint32_t msk[1] = {go ? 0xFFFFu << sh : 0u};
-  const uint32_t bits[1] = {go ? (uint32_t)lo << sh : 0u};
-  lds_mskor<1>(ret, off, msk, bits);
-  const int32_t old = (int32_t)((ret[0] >> sh) & 0xFFFFu);
-  const bool displaced = go && old != hi && old != lo;
-  const bool again = !roots || displaced;
-  const uint32_t back = !roots ? ((uint32_t)ga << 16) | (uint32_t)gb : ((uint32_t)old << 16) | (uint32_t)lo;
-  const uint64_t m = __ballot(again);
-  if (again) {
-    const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    stage[pos] = back;
+  int32_t pa[J], pb[J], ga[J], gb[J];
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    const uint32_t i = base + 64u * k + lane;
+    const uint32_t e = i < limit ? stage[i] : 0u;  // (0, 0): a no-op pair
+    pa[k] = (int32_t)(e >> 16);
+    pb[k] = (int32_t)(e & 0xFFFFu);
   }
-  return (uint32_t)__popcll(m);
+  int32_t a[J], b[J];
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    a[k] = pa[k];
+    b[k] = pb[k];
+    pa[k] = lds16_ld(par + a[k]);
+    pb[k] = lds16_ld(par + b[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    ga[k] = lds16_ld(par + pa[k]);
+    gb[k] = lds16_ld(par + pb[k]);
+  }
+  bool roots[J], go[J];
+  int32_t hi[J], lo[J];
+  uint32_t sh[J], off[J], msk[J], bits[J], ret[J];
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    if (ga[k] != pa[k]) lds16_st(par + a[k], ga[k]);  // halving: a now hangs under its grandparent
+    if (gb[k] != pb[k]) lds16_st(par + b[k], gb[k]);
+    roots[k] = ga[k] == pa[k] && gb[k] == pb[k];
+    hi[k] = max(pa[k], pb[k]);
+    lo[k] = min(pa[k], pb[k]);
+    go[k] = roots[k] && hi[k] != lo[k];
+    // the link: hi's 16-bit half of its word takes lo; a lane with nothing
+    // to link issues an empty mask on the word of its own end
+    sh[k] = (uint32_t)(hi[k] & 1) * 16u;
+    off[k] = (uint32_t)reinterpret_cast<uintptr_t>(par) + 4u * (uint32_t)(hi[k] >> 1);
+    msk[k] = go[k] ? 0xFFFFu << sh[k] : 0u;
+    bits[k] = go[k] ? (uint32_t)lo[k] << sh[k] : 0u;
+  }
+  lds_mskor<J>(ret, off, msk, bits);
+  uint32_t pos = base, total = 0;
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    const int32_t old = (int32_t)((ret[k] >> sh[k]) & 0xFFFFu);
+    const bool displaced = go[k] && old != hi[k] && old != lo[k];
+    const bool again = !roots[k] || displaced;
+    const uint32_t back = !roots[k] ? ((uint32_t)ga[k] << 16) | (uint32_t)gb[k]
+                                    : ((uint32_t)old << 16) | (uint32_t)lo[k];
+    const uint64_t m = __ballot(again);
+    if (again)
+      stage[pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = back;
+    const uint32_t c = (uint32_t)__popcll(m);
+    pos += c;
+    total += c;
+  }
+  return total;
 }
 
 // Joins everything left on the stack (at the end of a tile's bond stream).

@@ -193,11 +193,11 @@ def rect_triangle_csr(w, h, n=None):
 
 
 @pytest.mark.parametrize("w,h,cut", [(8192, 40, 0), (8192, 40, 8192 - 100), (6004, 33, 0), (6004, 33, 5),
-                                     (12288, 20, 0), (4100, 17, 4100), (4104, 48, 0)])
+                                     (12288, 36, 0), (4100, 37, 4100), (2052, 70, 0), (4104, 96, 0)])
 def test_csr_grid_tiles(ccl, w, h, cut):
-    """Grid tiles (16 rows x 4096 columns) on rectangular lattices: ragged
-    tile columns (w not a multiple of 4096) and tile rows (h not a multiple of
-    16), a partial last grid row whose missing sites make the last rows
+    """Grid tiles (32 rows x 2048 columns) on rectangular lattices: ragged
+    tile columns (w not a multiple of 2048) and tile rows (h not a multiple of
+    32), a partial last grid row whose missing sites make the last rows
     non-affine (the row path), a tile with no site, no mask, a device-drawn
     mask, and an occupancy view one byte off 4-byte alignment."""
     n = w * h - cut
