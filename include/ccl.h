@@ -50,7 +50,7 @@ typedef enum {
   CCL_ERR_OUT_OF_MEMORY = 3,      /* plan creation could not allocate */
   CCL_ERR_HIP = 4,                /* a HIP call failed; see ccl_last_hip_error() */
   CCL_ERR_NOT_SUPPORTED = 5,      /* device is not gfx950 */
-  CCL_ERR_TOO_LARGE = 6           /* input exceeds a fixed capacity (no-allocation entry point) */
+  CCL_ERR_TOO_LARGE = 6           /* input exceeds a fixed capacity (no-allocation entry point, capacity plan) */
 } ccl_status;
 
 /* ---------------------------------------------------------------- labeling */
@@ -229,6 +229,33 @@ typedef struct {
 ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
                            const int64_t* bond_off_host, const ccl_tuning* tuning,
                            ccl_plan* out);
+
+/*
+ * A plan for many layouts, for a loop that labels a changing group of
+ * instances (the ready requests of a serving tick) with one batched launch
+ * each time: the device tables are allocated once, sized for every layout of
+ * at most max_inst instances, max_sites sites and max_bonds bonds in total;
+ * ccl_plan_set_layout gives the plan the layout of its next launches.  Until
+ * a layout is set the plan has none and ccl_label_batched does nothing.
+ * Returns CCL_ERR_INVALID_VALUE for negative limits or a bad tuning,
+ * CCL_ERR_TOO_LARGE when the tables would exceed the work-item fields,
+ * CCL_ERR_OUT_OF_MEMORY / CCL_ERR_HIP when an allocation fails.
+ */
+ccl_status ccl_plan_create_capacity(int32_t max_inst, int64_t max_sites, int64_t max_bonds,
+                                    const ccl_tuning* tuning, ccl_plan* out);
+
+/*
+ * Sets the layout of a capacity plan without allocating and without a device
+ * synchronization: builds the work tables on the host (offsets as for
+ * ccl_plan_create), copies them into the plan's pinned staging and enqueues
+ * their upload on `stream`, which must be the stream of the launches that use
+ * the layout (launches of the previous layout already enqueued there run
+ * first).  The call waits only until the previous layout's upload has left
+ * the staging.  CCL_ERR_TOO_LARGE: the layout exceeds the plan's limits;
+ * CCL_ERR_INVALID_VALUE: bad offsets, or a plan made by ccl_plan_create.
+ */
+ccl_status ccl_plan_set_layout(ccl_plan plan, int32_t n_inst, const int64_t* site_off_host,
+                               const int64_t* bond_off_host, void* stream);
 
 /* Frees a plan (synchronizes the device first). NULL is a no-op. */
 ccl_status ccl_plan_destroy(ccl_plan plan);

@@ -83,6 +83,8 @@ def _load():
         "ccl_spans": (st, [i64, P, i64, P, i64, P, P, P, P]),
         "ccl_plan_create": (st, [i32, P, P, P, P]),
         "ccl_plan_destroy": (st, [P]),
+        "ccl_plan_create_capacity": (st, [i32, i64, i64, P, P]),
+        "ccl_plan_set_layout": (st, [P, i32, P, P, P]),
         "ccl_plan_get_tuning": (st, [P, P]),
         "ccl_plan_check": (st, [P, P]),
         "ccl_label_batched": (st, [P, P, P, P, P, P]),
@@ -384,8 +386,8 @@ class Plan:
             raise ValueError("site_off and bond_off must be 1-D with K+1 entries")
         if isinstance(tuning, dict):
             tuning = Tuning(**tuning)
-        self.device = torch.device(device) if device is not None else torch.device(
-            "cuda", torch.cuda.current_device())
+        d = torch.device(device) if device is not None else torch.device("cuda")
+        self.device = d if d.index is not None else torch.device("cuda", torch.cuda.current_device())
         self.n_inst = len(so) - 1
         self.total_sites = int(so[-1])
         self.total_bonds = int(bo[-1])
@@ -395,6 +397,38 @@ class Plan:
             _check(_lib.ccl_plan_create(self.n_inst, pso, pbo,
                                         ctypes.byref(tuning) if tuning is not None else None,
                                         ctypes.byref(self._h)), "ccl_plan_create")
+
+    @classmethod
+    def with_capacity(cls, max_inst: int, max_sites: int, max_bonds: int,
+                      tuning: Tuning | dict | None = None, device=None) -> "Plan":
+        """A plan for many layouts (ccl_plan_create_capacity): give it each
+        launch's layout with set_layout."""
+        if isinstance(tuning, dict):
+            tuning = Tuning(**tuning)
+        self = cls.__new__(cls)
+        d = torch.device(device) if device is not None else torch.device("cuda")
+        self.device = d if d.index is not None else torch.device("cuda", torch.cuda.current_device())
+        self.n_inst, self.total_sites, self.total_bonds = 0, 0, 0
+        self._site_off = self._bond_off = np.zeros(1, np.int64)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ccl_plan_create_capacity(int(max_inst), int(max_sites), int(max_bonds),
+                                                 ctypes.byref(tuning) if tuning is not None else None,
+                                                 ctypes.byref(self._h)), "ccl_plan_create_capacity")
+        return self
+
+    def set_layout(self, site_off, bond_off, stream=None) -> None:
+        """The layout of the next launches of a capacity plan
+        (ccl_plan_set_layout), uploaded on `stream`."""
+        so, pso = _host_i64(site_off)
+        bo, pbo = _host_i64(bond_off)
+        if so.shape != bo.shape or so.ndim != 1 or len(so) < 1:
+            raise ValueError("site_off and bond_off must be 1-D with K+1 entries")
+        with torch.cuda.device(self.device):
+            _check(_lib.ccl_plan_set_layout(self._h, len(so) - 1, pso, pbo, _stream(stream, self.device)),
+                   "ccl_plan_set_layout")
+        self.n_inst, self.total_sites, self.total_bonds = len(so) - 1, int(so[-1]), int(bo[-1])
+        self._site_off, self._bond_off = so, bo
 
     @property
     def tuning(self) -> Tuning:

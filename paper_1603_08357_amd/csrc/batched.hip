@@ -29,8 +29,10 @@
 // the kernel always drains even if a publication went wrong.  The host reads
 // the error word with ccl_plan_check().
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -501,28 +503,43 @@ __global__ void __launch_bounds__(512) k_batched_cross(BatchTileArgs a) {
 
 // ---------------------------------------------------------------- plan
 
+// Device tables of a plan, sized for capacities: a plan made for one layout
+// has exactly that layout's sizes; a capacity plan has bounds that any
+// layout within its limits fits, and takes a new layout per launch.
+struct PlanCaps {
+  int32_t inst = 0;
+  int64_t items = 0, tiles = 0, tiled = 0, ranges = 0;
+};
+
 struct ccl_plan_s {
   int device = -1;
-  int32_t n_inst = 0;
   ccl_tuning tuning{};
+  PlanCaps cap;
+  int64_t max_sites = 0, max_bonds = 0;  // capacity plans: the limits a layout must keep
+  bool reusable = false;
+  // the current layout
+  int32_t n_inst = 0;
   int64_t total_sites = 0, total_bonds = 0;
   int64_t n_items = 0;
   int64_t phase_end[3] = {0, 0, 0};  // phased schedule: items [end[p-1], end[p]) form phase p
+  int64_t n_tiles = 0;               // tiled schedule: tile items
+  int32_t n_tiled = 0;               // instances split into tiles
   unsigned grid = 0;
   void* dev_block = nullptr;  // one allocation holding every table below
   int64_t* d_site_off = nullptr;
   int64_t* d_bond_off = nullptr;
   uint64_t* d_items = nullptr;
-  uint32_t* d_ctl = nullptr;  // [0..2] queue heads, [3] error word
-  int32_t* d_done = nullptr;  // init_done[K], merge_done[K]
-  // tiled schedule
-  int64_t n_tiles = 0;        // tile items
-  int32_t n_tiled = 0;        // instances split into tiles
   int4* d_tiles = nullptr;    // (instance, tile, range index, 0)
   int4* d_tinst = nullptr;    // (instance, first tile item, tiles, first range index)
+  uint32_t* d_ctl = nullptr;  // [0..2] queue heads, [3] error word
+  int32_t* d_done = nullptr;  // init_done[K], merge_done[K]
   int64_t* d_ranges = nullptr;
   int32_t* d_counts = nullptr;
   int2* d_pairs = nullptr;
+  // capacity plans: pinned staging of the uploaded tables, and the event of
+  // the last upload (the staging is rewritten only after it has been read)
+  char* stage = nullptr;
+  hipEvent_t staged = nullptr;
 };
 
 using namespace ccl;
@@ -562,73 +579,75 @@ static bool tuning_ok(const ccl_tuning& t, const DeviceInfo& d) {
   return true;
 }
 
-extern "C" {
-
-ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
-                           const int64_t* bond_off_host, const ccl_tuning* tuning,
-                           ccl_plan* out) {
-  if (out == nullptr || n_inst < 0) return CCL_ERR_INVALID_VALUE;
-  *out = nullptr;
-  if (site_off_host == nullptr || bond_off_host == nullptr) return CCL_ERR_INVALID_VALUE;
-  if (site_off_host[0] != 0 || bond_off_host[0] != 0) return CCL_ERR_INVALID_VALUE;
-  for (int32_t k = 0; k < n_inst; ++k) {
-    const int64_t n = site_off_host[k + 1] - site_off_host[k];
-    const int64_t m = bond_off_host[k + 1] - bond_off_host[k];
-    if (n < 0 || n > INT32_MAX || m < 0 || (m > 0 && n == 0)) return CCL_ERR_INVALID_VALUE;
-  }
-  const DeviceInfo* d = current_device();
-  if (!d) return CCL_ERR_HIP;
-  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
-  const ccl_tuning t = resolve_tuning(tuning, *d);
-  if (!tuning_ok(t, *d)) return CCL_ERR_INVALID_VALUE;
-  for (int32_t k = 0; k < n_inst; ++k) {  // chunk ids must fit the 30-bit field
-    const int64_t n = site_off_host[k + 1] - site_off_host[k];
-    const int64_t m = bond_off_host[k + 1] - bond_off_host[k];
-    if ((n + t.sites_per_chunk - 1) / t.sites_per_chunk >= (1 << 30) ||
-        (m + t.bonds_per_chunk - 1) / t.bonds_per_chunk >= (1 << 30))
-      return CCL_ERR_INVALID_VALUE;
-  }
-
-  // instances by decreasing size; small ones are labelled in LDS
-  std::vector<int32_t> order(n_inst);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return site_off_host[x + 1] - site_off_host[x] > site_off_host[y + 1] - site_off_host[y];
-  });
-  std::vector<int32_t> large, small;
-  for (int32_t k : order) {
-    const int64_t n = site_off_host[k + 1] - site_off_host[k];
-    if (n == 0) continue;
-    (n <= t.small_sites ? small : large).push_back(k);
-  }
-  auto n_init = [&](int32_t k) {
-    return (site_off_host[k + 1] - site_off_host[k] + t.sites_per_chunk - 1) / t.sites_per_chunk;
-  };
-  auto n_merge = [&](int32_t k) {
-    return (bond_off_host[k + 1] - bond_off_host[k] + t.bonds_per_chunk - 1) / t.bonds_per_chunk;
-  };
-  auto emit = [](std::vector<uint64_t>& v, int32_t k, uint32_t kind, int64_t count) {
-    for (int64_t c = 0; c < count; ++c) v.push_back(pack_item(k, kind, (uint32_t)c));
-  };
+// The host tables of one layout.
+struct PlanTables {
   std::vector<uint64_t> items;
   int64_t phase_end[3] = {0, 0, 0};
   std::vector<int4> tile_items, tiled;
   int64_t n_ranges = 0;
+};
+
+// Offsets start at 0, never decrease, instances fit int32 ids, and an
+// instance with bonds has sites (checked before any device call).
+static ccl_status check_offsets(int32_t n_inst, const int64_t* so, const int64_t* bo) {
+  if (n_inst < 0 || so == nullptr || bo == nullptr) return CCL_ERR_INVALID_VALUE;
+  if (so[0] != 0 || bo[0] != 0) return CCL_ERR_INVALID_VALUE;
+  for (int32_t k = 0; k < n_inst; ++k) {
+    const int64_t n = so[k + 1] - so[k];
+    const int64_t m = bo[k + 1] - bo[k];
+    if (n < 0 || n > INT32_MAX || m < 0 || (m > 0 && n == 0)) return CCL_ERR_INVALID_VALUE;
+  }
+  return CCL_OK;
+}
+
+// Chunk ids must fit the 30-bit field of a work item.
+static ccl_status check_chunks(int32_t n_inst, const int64_t* so, const int64_t* bo, const ccl_tuning& t) {
+  for (int32_t k = 0; k < n_inst; ++k) {
+    const int64_t n = so[k + 1] - so[k];
+    const int64_t m = bo[k + 1] - bo[k];
+    if ((n + t.sites_per_chunk - 1) / t.sites_per_chunk >= (1 << 30) ||
+        (m + t.bonds_per_chunk - 1) / t.bonds_per_chunk >= (1 << 30))
+      return CCL_ERR_INVALID_VALUE;
+  }
+  return CCL_OK;
+}
+
+static ccl_status build_tables(const ccl_tuning& t, int32_t n_inst, const int64_t* so,
+                               const int64_t* bo, PlanTables& pt) {
+  // instances by decreasing size; small ones are labelled in LDS
+  std::vector<int32_t> order(n_inst);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return so[x + 1] - so[x] > so[y + 1] - so[y];
+  });
+  std::vector<int32_t> large, small;
+  for (int32_t k : order) {
+    const int64_t n = so[k + 1] - so[k];
+    if (n == 0) continue;
+    (n <= t.small_sites ? small : large).push_back(k);
+  }
+  auto n_init = [&](int32_t k) { return (so[k + 1] - so[k] + t.sites_per_chunk - 1) / t.sites_per_chunk; };
+  auto n_merge = [&](int32_t k) { return (bo[k + 1] - bo[k] + t.bonds_per_chunk - 1) / t.bonds_per_chunk; };
+  auto emit = [](std::vector<uint64_t>& v, int32_t k, uint32_t kind, int64_t count) {
+    for (int64_t c = 0; c < count; ++c) v.push_back(pack_item(k, kind, (uint32_t)c));
+  };
+  std::vector<uint64_t>& items = pt.items;
+  int64_t* phase_end = pt.phase_end;
   if (t.schedule == kScheduleTiled) {
     // phase 1: SMALL items (the tile items run in their own launch); phase 3:
     // FLATTEN items of the instances of more than one tile
     for (int32_t k : small) emit(items, k, kItemSmall, 1);
     phase_end[0] = phase_end[1] = (int64_t)items.size();
     for (int32_t k : large) {
-      const int64_t n = site_off_host[k + 1] - site_off_host[k];
+      const int64_t n = so[k + 1] - so[k];
       const int32_t nt = (int32_t)((n + kBatchTile - 1) / kBatchTile);
-      tiled.push_back(make_int4(k, (int32_t)tile_items.size(), nt, (int32_t)n_ranges));
-      for (int32_t tt = 0; tt < nt; ++tt) tile_items.push_back(make_int4(k, tt, (int32_t)(n_ranges + tt), 0));
-      n_ranges += nt + 1;
+      pt.tiled.push_back(make_int4(k, (int32_t)pt.tile_items.size(), nt, (int32_t)pt.n_ranges));
+      for (int32_t tt = 0; tt < nt; ++tt) pt.tile_items.push_back(make_int4(k, tt, (int32_t)(pt.n_ranges + tt), 0));
+      pt.n_ranges += nt + 1;
       if (nt > 1) emit(items, k, kItemFlatten, n_init(k));
     }
     phase_end[2] = (int64_t)items.size();
-    if ((int64_t)tile_items.size() >= INT32_MAX || n_ranges >= INT32_MAX) return CCL_ERR_INVALID_VALUE;
+    if ((int64_t)pt.tile_items.size() >= INT32_MAX || pt.n_ranges >= INT32_MAX) return CCL_ERR_INVALID_VALUE;
   } else if (t.schedule == kScheduleFused) {
     const int64_t L = (int64_t)large.size();
     for (int64_t s = 0; s < L + 2; ++s) {
@@ -650,73 +669,239 @@ ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
     phase_end[2] = (int64_t)items.size();
   }
   if ((int64_t)items.size() >= (int64_t)UINT32_MAX) return CCL_ERR_INVALID_VALUE;
+  return CCL_OK;
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of the tables in the device block (and, for the first five,
+// in the pinned staging of a capacity plan).
+struct PlanLayout {
+  size_t site_off, bond_off, items, tiles, tinst, upload_end, ctl, ranges, counts, pairs, total;
+};
+
+static PlanLayout plan_layout(const PlanCaps& c) {
+  PlanLayout L{};
+  size_t o = 0;
+  const size_t off_bytes = up256(sizeof(int64_t) * (size_t)(c.inst + 1));
+  L.site_off = o;
+  o += off_bytes;
+  L.bond_off = o;
+  o += off_bytes;
+  L.items = o;
+  o += up256(sizeof(uint64_t) * (size_t)c.items);
+  L.tiles = o;
+  o += up256(sizeof(int4) * (size_t)c.tiles);
+  L.tinst = o;
+  o += up256(sizeof(int4) * (size_t)c.tiled);
+  L.upload_end = o;
+  L.ctl = o;
+  o += up256(256 + sizeof(int32_t) * 2 * (size_t)c.inst);
+  L.ranges = o;
+  o += up256(sizeof(int64_t) * (size_t)c.ranges);
+  L.counts = o;
+  o += up256(sizeof(int32_t) * (size_t)c.tiles);
+  L.pairs = o;
+  o += sizeof(int2) * (size_t)kTilePairs * (size_t)c.tiles;
+  L.total = o;
+  return L;
+}
+
+// Allocates the device block (and for capacity plans the staging and its
+// event) and points the plan's tables into it.
+static ccl_status plan_alloc(ccl_plan p) {
+  const PlanLayout L = plan_layout(p->cap);
+  hipError_t e = hipMalloc(&p->dev_block, L.total);
+  if (e != hipSuccess) return fail_hip(e);
+  char* b = static_cast<char*>(p->dev_block);
+  p->d_site_off = reinterpret_cast<int64_t*>(b + L.site_off);
+  p->d_bond_off = reinterpret_cast<int64_t*>(b + L.bond_off);
+  p->d_items = reinterpret_cast<uint64_t*>(b + L.items);
+  p->d_tiles = reinterpret_cast<int4*>(b + L.tiles);
+  p->d_tinst = reinterpret_cast<int4*>(b + L.tinst);
+  p->d_ctl = reinterpret_cast<uint32_t*>(b + L.ctl);
+  p->d_done = reinterpret_cast<int32_t*>(b + L.ctl + 256);
+  p->d_ranges = reinterpret_cast<int64_t*>(b + L.ranges);
+  p->d_counts = reinterpret_cast<int32_t*>(b + L.counts);
+  p->d_pairs = reinterpret_cast<int2*>(b + L.pairs);
+  e = hipMemset(b + L.ctl, 0, L.ranges - L.ctl);
+  if (e == hipSuccess && p->reusable) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&p->stage), L.upload_end, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e == hipSuccess ? CCL_OK : fail_hip(e);
+}
+
+static void plan_free(ccl_plan p) {
+  if (p->staged) (void)hipEventDestroy(p->staged);
+  if (p->stage) (void)hipHostFree(p->stage);
+  if (p->dev_block) (void)hipFree(p->dev_block);
+  delete p;
+}
+
+static void plan_take_layout(ccl_plan p, int32_t n_inst, const int64_t* so, const int64_t* bo,
+                             const PlanTables& pt) {
+  p->n_inst = n_inst;
+  p->total_sites = so[n_inst];
+  p->total_bonds = bo[n_inst];
+  p->n_items = (int64_t)pt.items.size();
+  for (int i = 0; i < 3; ++i) p->phase_end[i] = pt.phase_end[i];
+  p->n_tiles = (int64_t)pt.tile_items.size();
+  p->n_tiled = (int32_t)pt.tiled.size();
+}
+
+static bool fits(const PlanCaps& c, int32_t n_inst, const PlanTables& pt) {
+  return n_inst <= c.inst && (int64_t)pt.items.size() <= c.items && (int64_t)pt.tile_items.size() <= c.tiles &&
+         (int64_t)pt.tiled.size() <= c.tiled && pt.n_ranges <= c.ranges;
+}
+
+extern "C" {
+
+ccl_status ccl_plan_create(int32_t n_inst, const int64_t* site_off_host,
+                           const int64_t* bond_off_host, const ccl_tuning* tuning,
+                           ccl_plan* out) {
+  if (out == nullptr || n_inst < 0) return CCL_ERR_INVALID_VALUE;
+  *out = nullptr;
+  ccl_status st = check_offsets(n_inst, site_off_host, bond_off_host);
+  if (st != CCL_OK) return st;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  const ccl_tuning t = resolve_tuning(tuning, *d);
+  if (!tuning_ok(t, *d)) return CCL_ERR_INVALID_VALUE;
+  st = check_chunks(n_inst, site_off_host, bond_off_host, t);
+  if (st != CCL_OK) return st;
+  PlanTables pt;
+  st = build_tables(t, n_inst, site_off_host, bond_off_host, pt);
+  if (st != CCL_OK) return st;
 
   ccl_plan p = new (std::nothrow) ccl_plan_s();
   if (!p) return CCL_ERR_OUT_OF_MEMORY;
   p->device = d->device;
-  p->n_inst = n_inst;
   p->tuning = t;
-  p->total_sites = site_off_host[n_inst];
-  p->total_bonds = bond_off_host[n_inst];
-  p->n_items = (int64_t)items.size();
-  for (int i = 0; i < 3; ++i) p->phase_end[i] = phase_end[i];
   p->grid = (unsigned)(d->cu_count * t.blocks_per_cu);
-
-  const size_t off_bytes = sizeof(int64_t) * (size_t)(n_inst + 1);
-  const size_t item_bytes = sizeof(uint64_t) * items.size();
-  const size_t ctl_bytes = 256 + sizeof(int32_t) * 2 * (size_t)n_inst;
-  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t nt = tile_items.size();
-  const size_t tile_bytes = up(sizeof(int4) * nt) + up(sizeof(int4) * tiled.size()) +
-                            up(sizeof(int64_t) * (size_t)n_ranges) + up(sizeof(int32_t) * nt) +
-                            sizeof(int2) * (size_t)kTilePairs * nt;
-  const size_t total = up(off_bytes) * 2 + up(item_bytes) + up(ctl_bytes) + tile_bytes;
-  hipError_t e = hipMalloc(&p->dev_block, total);
-  if (e != hipSuccess) {
-    delete p;
-    return fail_hip(e);
+  p->cap.inst = n_inst;
+  p->cap.items = (int64_t)pt.items.size();
+  p->cap.tiles = (int64_t)pt.tile_items.size();
+  p->cap.tiled = (int64_t)pt.tiled.size();
+  p->cap.ranges = pt.n_ranges;
+  p->max_sites = site_off_host[n_inst];
+  p->max_bonds = bond_off_host[n_inst];
+  st = plan_alloc(p);
+  if (st != CCL_OK) {
+    plan_free(p);
+    return st;
   }
-  char* base = static_cast<char*>(p->dev_block);
-  p->d_site_off = reinterpret_cast<int64_t*>(base);
-  p->d_bond_off = reinterpret_cast<int64_t*>(base + up(off_bytes));
-  p->d_items = reinterpret_cast<uint64_t*>(base + 2 * up(off_bytes));
-  p->d_ctl = reinterpret_cast<uint32_t*>(base + 2 * up(off_bytes) + up(item_bytes));
-  p->d_done = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(p->d_ctl) + 256);
-  char* tb = reinterpret_cast<char*>(p->d_ctl) + up(ctl_bytes);
-  p->n_tiles = (int64_t)nt;
-  p->n_tiled = (int32_t)tiled.size();
-  p->d_tiles = reinterpret_cast<int4*>(tb);
-  tb += up(sizeof(int4) * nt);
-  p->d_tinst = reinterpret_cast<int4*>(tb);
-  tb += up(sizeof(int4) * tiled.size());
-  p->d_ranges = reinterpret_cast<int64_t*>(tb);
-  tb += up(sizeof(int64_t) * (size_t)n_ranges);
-  p->d_counts = reinterpret_cast<int32_t*>(tb);
-  tb += up(sizeof(int32_t) * nt);
-  p->d_pairs = reinterpret_cast<int2*>(tb);
-  e = hipMemcpy(p->d_site_off, site_off_host, off_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->d_bond_off, bond_off_host, off_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess && item_bytes)
-    e = hipMemcpy(p->d_items, items.data(), item_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(p->d_ctl, 0, up(ctl_bytes));
-  if (e == hipSuccess && nt) e = hipMemcpy(p->d_tiles, tile_items.data(), sizeof(int4) * nt, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !tiled.empty())
-    e = hipMemcpy(p->d_tinst, tiled.data(), sizeof(int4) * tiled.size(), hipMemcpyHostToDevice);
+  plan_take_layout(p, n_inst, site_off_host, bond_off_host, pt);
+  const size_t ob = sizeof(int64_t) * (size_t)(n_inst + 1);
+  hipError_t e = hipMemcpy(p->d_site_off, site_off_host, ob, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_bond_off, bond_off_host, ob, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pt.items.empty())
+    e = hipMemcpy(p->d_items, pt.items.data(), sizeof(uint64_t) * pt.items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pt.tile_items.empty())
+    e = hipMemcpy(p->d_tiles, pt.tile_items.data(), sizeof(int4) * pt.tile_items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pt.tiled.empty())
+    e = hipMemcpy(p->d_tinst, pt.tiled.data(), sizeof(int4) * pt.tiled.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    (void)hipFree(p->dev_block);
-    delete p;
+    plan_free(p);
     return fail_hip(e);
   }
   *out = p;
   return CCL_OK;
 }
 
+ccl_status ccl_plan_create_capacity(int32_t max_inst, int64_t max_sites, int64_t max_bonds,
+                                    const ccl_tuning* tuning, ccl_plan* out) {
+  if (out == nullptr) return CCL_ERR_INVALID_VALUE;
+  *out = nullptr;
+  if (max_inst < 0 || max_sites < 0 || max_bonds < 0) return CCL_ERR_INVALID_VALUE;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (!d->is_gfx950) return CCL_ERR_NOT_SUPPORTED;
+  const ccl_tuning t = resolve_tuning(tuning, *d);
+  if (!tuning_ok(t, *d)) return CCL_ERR_INVALID_VALUE;
+  // bounds over every layout of at most max_inst instances, max_sites sites
+  // and max_bonds bonds: an instance adds at most one partial chunk or tile
+  // to each count, and only instances above small_sites sites are tiled
+  const int64_t spc = t.sites_per_chunk, bpc = t.bonds_per_chunk;
+  PlanCaps c;
+  c.inst = max_inst;
+  c.items = 2 * ((max_sites + spc - 1) / spc) + (max_bonds + bpc - 1) / bpc + 4 * (int64_t)max_inst;
+  if (t.schedule == kScheduleTiled) {
+    c.tiled = std::min<int64_t>(max_inst, max_sites / ((int64_t)t.small_sites + 1));
+    c.tiles = (max_sites + kBatchTile - 1) / kBatchTile + c.tiled;
+    c.ranges = c.tiles + c.tiled;
+  }
+  if (c.items >= (int64_t)UINT32_MAX || c.tiles >= INT32_MAX || c.ranges >= INT32_MAX)
+    return CCL_ERR_TOO_LARGE;
+  ccl_plan p = new (std::nothrow) ccl_plan_s();
+  if (!p) return CCL_ERR_OUT_OF_MEMORY;
+  p->device = d->device;
+  p->tuning = t;
+  p->grid = (unsigned)(d->cu_count * t.blocks_per_cu);
+  p->cap = c;
+  p->max_sites = max_sites;
+  p->max_bonds = max_bonds;
+  p->reusable = true;
+  const ccl_status st = plan_alloc(p);
+  if (st != CCL_OK) {
+    plan_free(p);
+    return st;
+  }
+  *out = p;  // empty layout: ccl_label_batched does nothing until one is set
+  return CCL_OK;
+}
+
+ccl_status ccl_plan_set_layout(ccl_plan plan, int32_t n_inst, const int64_t* site_off_host,
+                               const int64_t* bond_off_host, void* stream) {
+  if (plan == nullptr || !plan->reusable) return CCL_ERR_INVALID_VALUE;
+  ccl_status st = check_offsets(n_inst, site_off_host, bond_off_host);
+  if (st != CCL_OK) return st;
+  const DeviceInfo* d = current_device();
+  if (!d) return CCL_ERR_HIP;
+  if (d->device != plan->device) return CCL_ERR_INVALID_VALUE;
+  st = check_chunks(n_inst, site_off_host, bond_off_host, plan->tuning);
+  if (st != CCL_OK) return st;
+  if (site_off_host[n_inst] > plan->max_sites || bond_off_host[n_inst] > plan->max_bonds ||
+      n_inst > plan->cap.inst)
+    return CCL_ERR_TOO_LARGE;
+  PlanTables pt;
+  st = build_tables(plan->tuning, n_inst, site_off_host, bond_off_host, pt);
+  if (st != CCL_OK) return st;
+  if (!fits(plan->cap, n_inst, pt)) return CCL_ERR_TOO_LARGE;
+  // the previous upload has read the staging before it is rewritten
+  hipError_t e = hipEventSynchronize(plan->staged);
+  if (e != hipSuccess) return fail_hip(e);
+  const PlanLayout L = plan_layout(plan->cap);
+  const size_t ob = sizeof(int64_t) * (size_t)(n_inst + 1);
+  struct Part {
+    size_t off, bytes;
+    const void* src;
+  } parts[5] = {{L.site_off, ob, site_off_host},
+                {L.bond_off, ob, bond_off_host},
+                {L.items, sizeof(uint64_t) * pt.items.size(), pt.items.data()},
+                {L.tiles, sizeof(int4) * pt.tile_items.size(), pt.tile_items.data()},
+                {L.tinst, sizeof(int4) * pt.tiled.size(), pt.tiled.data()}};
+  hipStream_t s = (hipStream_t)stream;
+  char* dev = static_cast<char*>(plan->dev_block);
+  for (const Part& q : parts) {
+    if (q.bytes == 0) continue;
+    std::memcpy(plan->stage + q.off, q.src, q.bytes);
+    e = hipMemcpyAsync(dev + q.off, plan->stage + q.off, q.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e);
+  }
+  e = hipEventRecord(plan->staged, s);
+  if (e != hipSuccess) return fail_hip(e);
+  plan_take_layout(plan, n_inst, site_off_host, bond_off_host, pt);
+  return CCL_OK;
+}
+
 ccl_status ccl_plan_destroy(ccl_plan plan) {
   if (plan == nullptr) return CCL_OK;
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipFree(plan->dev_block);
-  delete plan;
+  plan_free(plan);
   return e == hipSuccess ? CCL_OK : fail_hip(e);
 }
 

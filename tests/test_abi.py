@@ -101,6 +101,15 @@ def test_plan_argument_errors(lib):
     assert lib.ccl_plan_create(1, None, None, None, ctypes.byref(plan)) == INVALID
     assert lib.ccl_label_batched(None, None, None, None, None, None) == INVALID
     assert lib.ccl_plan_destroy(None) == 0
+    # capacity plans: negative limits and a missing plan are refused on the host
+    lib.ccl_plan_create_capacity.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    lib.ccl_plan_set_layout.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.ccl_plan_create_capacity(-1, 10, 10, None, ctypes.byref(plan)) == INVALID
+    assert lib.ccl_plan_create_capacity(4, -1, 10, None, ctypes.byref(plan)) == INVALID
+    assert lib.ccl_plan_create_capacity(4, 10, 10, None, None) == INVALID
+    assert lib.ccl_plan_set_layout(None, 2, so, bo, None) == INVALID
 
 
 def test_validation_argument_errors(lib):

@@ -816,6 +816,77 @@ def test_serving_mixed_equals_alone(ccl):
         np.testing.assert_array_equal(j.labels, oracle.label_edges(j.n_sites, j.src, j.dst, j.occ))
 
 
+def test_serving_ticks_under_a_binding_budget(ccl):
+    """All requests present at once, a budget that holds about a third of
+    them and small tick limits: small requests ride in batched ticks (one
+    ccl_label_batched launch of a capacity plan per tick), the budget is
+    what bounds the work in flight, and every result equals the oracle's."""
+    from paper_1603_08357_amd.serving import GpuExecutor, Job, Scheduler
+
+    reqs = gen.request_trace(90, rate=1e9, base_seed=23, n_max=300_000)
+    jobs = []
+    for r in reqs:
+        g = gen.request_graph(r)
+        jobs.append(Job(r.rid, 0.0, g.n_sites, g.src, g.dst, g.occ))
+    jobs.append(Job(1000, 0.0, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint8)))
+    jobs.append(Job(1001, 0.0, 7, np.zeros(0, np.int32), np.zeros(0, np.int32), None))
+    ex = GpuExecutor(n_streams=3, max_sites=max(j.n_sites for j in jobs), tick_sites=1 << 15, tick_jobs=12,
+                     tick_total_sites=1 << 18, tick_total_bonds=1 << 20)
+    budget = sum(j.bytes for j in jobs) // 3
+    sch = Scheduler(ex, budget, max_slots=64)
+    _say(f"serving {len(jobs)} requests, budget {budget} bytes")
+    done = sch.serve(jobs)
+    assert len(done) == len(jobs) and all(j.status == "done" for j in jobs)
+    assert sch.ticks > 0 and sch.peak_used <= budget and sch.peak_used > budget // 2
+    assert sum(j.batched > 1 for j in jobs) > 10
+    for j in jobs:
+        np.testing.assert_array_equal(j.labels, oracle.label_edges(j.n_sites, j.src, j.dst, j.occ),
+                                      err_msg=f"request {j.rid} ({j.n_sites} sites, tick of {j.batched})")
+        assert j.t_kernel_ms >= 0 and j.t_h2d_ms >= 0
+
+
+@pytest.mark.parametrize("schedule", [3, 2])
+def test_capacity_plan_takes_a_layout_per_launch(ccl, schedule):
+    """One capacity plan, five layouts set and launched back to back on one
+    stream with no synchronization in between (each layout's tables are
+    uploaded behind the previous launch); every batch equals the oracle.
+    Layouts beyond the plan's limits and a plan made for one layout are
+    refused."""
+    plan = ccl.Plan.with_capacity(48, 2_000_000, 6_000_000, dict(schedule=schedule))
+    stream = torch.cuda.Stream()
+    cases = []
+    for k, (count, seed, ls) in enumerate(((40, 1, (16, 64, 128)), (3, 2, (512,)), (48, 3, (16, 64, 256)),
+                                           (1, 4, (64,)), (17, 5, (128, 256)))):
+        specs = gen.batch_specs(count, base_seed=seed, ls=ls)
+        so, bo, src, dst, occ = _batch(specs)
+        cases.append((so, bo, dev(src), dev(dst), dev(occ), oracle.label_batched(so, bo, src, dst, occ)))
+    torch.cuda.synchronize()
+    outs = []
+    _say(f"capacity plan, schedule {schedule}: {len(cases)} layouts back to back")
+    for so, bo, src, dst, occ, _ in cases:
+        plan.set_layout(so, bo, stream=stream)
+        outs.append(plan.label(src, dst, occ, stream=stream))
+    torch.cuda.synchronize()
+    for k, (case, out) in enumerate(zip(cases, outs)):
+        np.testing.assert_array_equal(out.cpu().numpy(), case[5], err_msg=f"layout {k}")
+    assert plan.check() == 0
+    big = gen.batch_specs(49, base_seed=6, ls=(16,))
+    so, bo = gen.batch_offsets(big)
+    with pytest.raises(ccl.CclError) as e:
+        plan.set_layout(so, bo)  # 49 instances > 48
+    assert e.value.status == 6
+    so, bo = gen.batch_offsets(gen.batch_specs(2, base_seed=7, ls=(1024,)))
+    with pytest.raises(ccl.CclError) as e:
+        plan.set_layout(so, bo)  # 2^21 sites > 2,000,000
+    assert e.value.status == 6
+    plan.close()
+    fixed = ccl.Plan(*gen.batch_offsets(gen.batch_specs(2, base_seed=8, ls=(16,))))
+    with pytest.raises(ccl.CclError) as e:
+        fixed.set_layout(*gen.batch_offsets(gen.batch_specs(2, base_seed=8, ls=(16,))))
+    assert e.value.status == 1
+    fixed.close()
+
+
 def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
     from paper_1603_08357_amd import autotune
     monkeypatch.setenv("CCL_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))

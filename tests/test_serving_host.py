@@ -162,3 +162,67 @@ def test_autotune_candidates_and_layout_key():
     k2 = autotune.layout_key([0, 110, 320, 1270])  # sizes 110, 210, 950
     assert k1 == k2 and k1.startswith("K3-")
     assert autotune.layout_key([0]) == "empty"
+
+
+class FakeBatchExecutor(FakeExecutor):
+    """FakeExecutor that also takes ticks of small jobs."""
+
+    tick_limits = {"sites": 1000, "jobs": 4, "total_sites": 2500, "total_bonds": 10**9}
+
+    def __init__(self, clock, cost=1e-6):
+        super().__init__(clock, cost)
+        self.batches = []
+
+    def launch_batch(self, jobs):
+        assert 1 < len(jobs) <= self.tick_limits["jobs"]
+        assert all(j.n_sites <= self.tick_limits["sites"] for j in jobs)
+        assert sum(j.n_sites for j in jobs) <= self.tick_limits["total_sites"]
+        self.batches.append([j.rid for j in jobs])
+        end = self.clock() + self.cost * max(sum(j.n_sites for j in jobs), 1)
+        for j in jobs:
+            self.inflight.add(j.rid)
+        self.max_inflight = max(self.max_inflight, len(self.inflight))
+        return ("batch", tuple(j.rid for j in jobs), end)
+
+    def done(self, h):
+        return self.clock() >= h[-1]
+
+    def finish(self, h):
+        if h[0] == "batch":
+            for r in h[1]:
+                self.inflight.discard(r)
+            return [np.array([r], np.int32) for r in h[1]]
+        return super().finish(h)
+
+
+def test_ticks_group_small_jobs_in_order_within_budget():
+    clock = FakeClock()
+    ex = FakeBatchExecutor(clock)
+    sizes = [300, 200, 900, 5000, 100, 100, 100, 100, 100, 700, 20_000, 50, 60] * 3
+    jobs = [make_job(i, n, arrival=0.0) for i, n in enumerate(sizes)]
+    budget = sum(j.bytes for j in jobs) // 2
+    s = Scheduler(ex, budget, max_slots=3, clock=clock)
+    for j in jobs:
+        s.submit(j)
+    order = []
+    while not s.idle:
+        before = set(s.running)
+        s.poll()
+        for key in set(s.running) - before:
+            order.extend(j.rid for j in s.running[key][0])
+        assert s.used <= budget and len(s.running) <= 3
+        clock.t += 1e-4
+    # only small jobs riding in a tick may pass earlier jobs, and only larger
+    # ones that were not at the head of the queue
+    pos = {r: i for i, r in enumerate(order)}
+    for a in range(len(sizes)):
+        for b in range(a + 1, len(sizes)):
+            if pos[b] < pos[a]:
+                assert sizes[a] > ex.tick_limits["sites"] and sizes[b] <= ex.tick_limits["sites"], (a, b)
+    assert s.ticks == len(ex.batches) > 0
+    assert all(len(b) > 1 for b in ex.batches)
+    for j in jobs:
+        assert j.status == "done" and list(j.labels) == [j.rid]
+        assert (j.batched > 1) == any(j.rid in b for b in ex.batches)
+    # a job too large for a tick never rides in one
+    assert not any(r in b for b in ex.batches for r, n in enumerate(sizes) if n > 1000)
