@@ -907,8 +907,9 @@ def test_autotune_picks_a_correct_tuning(ccl, tmp_path, monkeypatch):
 # ------------------------------------------------------------ concurrency
 
 def test_concurrent_streams_match_oracle(ccl):
-    """Edge-list, multi-tile CSR, neighbour-list (the paper's schedule) and
-    batched-plan jobs in flight on eight streams at once: every result equals
+    """Edge-list, multi-tile CSR (slabs and grid tiles), neighbour-list (the
+    paper's schedule) and batched-plan jobs (tiled schedule) in flight on
+    eight streams at once: every result equals
     the oracle's.  (A merge-step compression store landing after the flatten's
     final root store showed up only under concurrent kernels; every label
     store of the labeling kernels is device-scope for that reason.)  Stops at
@@ -920,6 +921,8 @@ def test_concurrent_streams_match_oracle(ccl):
     for L, p in [(300, 0.3473), (512, 0.5209)]:
         g = gen.triangle_csr_realization(L, p, L)
         jobs.append(("csr", g, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)))
+    g = gen.triangle_csr_realization(2176, 0.3473, 5)  # grid tiles: rows wider than a tile
+    jobs.append(("csr_grid", g, oracle.label_csr(g.n_sites, g.row_ptr, g.col, g.occ)))
     e = gen.bethe_random_regular(250_000, 3, 0.55, 47)
     nn, occ_ell = gen.ell_from_edges(e.n_sites, e.src, e.dst, e.occ, 3)
     jobs.append(("ell", (nn, occ_ell), oracle.label_edges(e.n_sites, e.src, e.dst, e.occ)))
@@ -934,7 +937,7 @@ def test_concurrent_streams_match_oracle(ccl):
         ws = None
         if kind == "edges":
             ins = (dev(g.src), dev(g.dst), dev(g.occ))
-        elif kind == "csr":
+        elif kind in ("csr", "csr_grid"):
             ins = (dev(g.row_ptr), dev(g.col), dev(g.occ))
             ws = [torch.empty(max(ccl.csr_workspace_bytes(g.n_sites, len(g.col)), 8), dtype=torch.uint8,
                               device="cuda") for _ in range(S)]
@@ -946,7 +949,7 @@ def test_concurrent_streams_match_oracle(ccl):
         outs = [torch.empty(len(want), dtype=torch.int32, device="cuda") for _ in range(S)]
         bufs.append((ins, ws, outs))
     torch.cuda.synchronize()
-    _say(f"concurrent: {len(jobs)} jobs (edge list, CSR, neighbour list, batched) x {S} streams")
+    _say(f"concurrent: {len(jobs)} jobs (edge list, CSR slabs and grid tiles, neighbour list, batched) x {S} streams")
     for it in range(40):
         picks = []
         for s in range(S):
@@ -958,6 +961,9 @@ def test_concurrent_streams_match_oracle(ccl):
                     ccl.label(ins[0], ins[1], g.n_sites, ins[2], out=outs[s], stream=streams[s])
                 elif kind == "csr":
                     ccl.label_csr(ins[0], ins[1], ins[2], out=outs[s], workspace=ws[s], stream=streams[s])
+                elif kind == "csr_grid":
+                    ccl.label_csr(ins[0], ins[1], ins[2], out=outs[s], workspace=ws[s], stream=streams[s],
+                                  grid_width=2176)
                 elif kind == "ell":
                     ccl.label_ell(ins[0], ins[1], out=outs[s], stream=streams[s])
                 else:

@@ -80,16 +80,16 @@ def test_pins_reject_mutant(name):
 
 # ---- step (i) of the paper's schedule: the residual list's lowest entry
 
-def _ell_init_mutant(n, z, nn, occ, *, pick="lowest", ignore_occ=False, or_equal=False):
+def _ell_init_mutant(n, z, nn, occ, *, pick="lowest", ignore_occ=False):
     """oracle.ell_init's definition with one planted error: the entry taken
     from the residual list ("highest", "first" or "last" listed instead of
-    the lowest), the mask ignored, or the site itself counted as lower."""
+    the lowest), or the mask ignored."""
     nn = np.asarray(nn).reshape(z, n)
     on = np.ones(nn.shape, bool) if ignore_occ else np.asarray(occ).reshape(z, n) != 0
     out = np.arange(n, dtype=np.int32)
     for i in range(n):
         lower = [int(nn[k, i]) for k in range(z)
-                 if on[k, i] and 0 <= nn[k, i] and (nn[k, i] <= i if or_equal else nn[k, i] < i)]
+                 if on[k, i] and 0 <= nn[k, i] < i]
         if not lower:
             continue
         out[i] = {"lowest": min, "highest": max, "first": lambda l: l[0], "last": lambda l: l[-1]}[pick](lower)
