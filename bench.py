@@ -108,7 +108,7 @@ def load_traffic(kernel: str, workload: str):
 
 
 COPY_PROBE_BYTES = 1 << 30  # the copy probe reads and writes this much
-KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
+KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_tile_grid": "ccl_csr_tile", "k_csr_cross": "ccl_csr_cross",
                 "k_ell_init": "ccl_ell_init", "k_ell_reduce": "ccl_ell_reduce",
                 "k_sizes_own": "ccl_sizes_own", "k_sizes_foreign": "ccl_sizes_foreign",
                 "k_flatten": "ccl_flatten", "k_flatten_window": "ccl_flatten_window",

@@ -371,6 +371,8 @@ constexpr int kGridTw = 1 << kGridTwShift;
 constexpr int kGridTh = kCsrTile / kGridTw;
 static_assert(kGridTh <= 64, "one lane per tile row in the header loads");
 static_assert(kGridTw >= kTileBlock && (4 * kTileBlock) % kGridTw == 0, "the epilogue's runs cover whole rows");
+constexpr int kEpiRuns = 2;    // runs of 4 kTileBlock slots per epilogue pass
+constexpr int kEpiRounds = 3;  // lockstep LDS rounds before the fallback chases
 
 struct GridGeo {
   int64_t n;        // sites
@@ -529,8 +531,9 @@ __global__ void __launch_bounds__(kTileBlock)
       }
     return p;
   };
+  auto group = [&](SlotPos p) { return p.r * kTileBlock + tid; };
   auto load = [&](SlotPos p, int4& cv, uint32_t& ov) {
-    const int32_t g = p.r * kTileBlock + tid;
+    const int32_t g = group(p);
     const bool in = p.s < rows && 4 * g < deg * row_len(p.s);
     const uint32_t off = in ? (uint32_t)(deg * p.s * w32 + 4 * g) : kOffNone;
     cv = buf_i32x4(rcol, off * 4u);
@@ -604,7 +607,7 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
       for (int u = 0; u < G; ++u, at = advance(at, 1)) {
         const int32_t s = at.s;
-        const int32_t g = at.r * kTileBlock + tid;
+        const int32_t g = group(at);
         const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
         uint32_t act = 0;  // bit j: bond j of the group is occupied and inside the tile
         uint32_t packed[4];
@@ -625,7 +628,7 @@ __global__ void __launch_bounds__(kTileBlock)
 #pragma unroll
         for (int u = 0; u < G; ++u, at = advance(at, 1)) {
           const int32_t s = at.s;
-          const int32_t g = at.r * kTileBlock + tid;
+          const int32_t g = group(at);
           const int32_t c4[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
 #pragma unroll
           for (int j = 0; j < 4; ++j)
@@ -685,9 +688,9 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   __syncthreads();
-  // the tile's labels: each site's tile-local root.  A pass takes two runs
-  // of 4 kTileBlock consecutive slots, four per lane (a run covers whole
-  // tile rows), eight chases resolved together; 16-byte stores when the
+  // the tile's labels: each site's tile-local root.  A pass takes kEpiRuns
+  // runs of 4 kTileBlock consecutive slots, four per lane (a run covers whole
+  // tile rows), all their chases resolved together; 16-byte stores when the
   // label array and the row length allow it
   const bool vec = ((reinterpret_cast<uintptr_t>(label + u0) & 15) == 0) && (geo.w % 4 == 0);
   const __amdgpu_buffer_rsrc_t rl = make_rsrc(label + u0, vec && fast ? (uint32_t)span_sites * 4u : 0u);
@@ -695,12 +698,13 @@ __global__ void __launch_bounds__(kTileBlock)
     return (int32_t)(u0 + (int64_t)(t >> kGridTwShift) * geo.w + (t & (kGridTw - 1)));
   };
   constexpr int32_t kRun = 4 * kTileBlock;  // slots per run
+  constexpr int E = kEpiRuns;
   const int32_t n_runs = (rows * kGridTw + kRun - 1) / kRun;
-  for (int32_t q0 = 0; q0 < n_runs; q0 += 2) {
-    int32_t x[8];
+  for (int32_t q0 = 0; q0 < n_runs; q0 += E) {
+    int32_t x[4 * E];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int32_t t = min(q0 + h, n_runs - 1) * kRun + 4 * tid;  // a missing second run repeats the first
+    for (int h = 0; h < E; ++h) {
+      const int32_t t = min(q0 + h, n_runs - 1) * kRun + 4 * tid;  // a missing run repeats the last
       const uint2 wv = reinterpret_cast<const uint2*>(par)[t >> 2];
       x[4 * h + 0] = (int32_t)(wv.x & 0xFFFFu);
       x[4 * h + 1] = (int32_t)(wv.x >> 16);
@@ -708,16 +712,16 @@ __global__ void __launch_bounds__(kTileBlock)
       x[4 * h + 3] = (int32_t)(wv.y >> 16);
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < kEpiRounds; ++r)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
+      for (int k = 0; k < 4 * E; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 4 * E; ++k) {
       const int32_t p = lds16_ld(par + x[k]);
       if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < E; ++h) {
       if (q0 + h >= n_runs) continue;
       const int32_t t = (q0 + h) * kRun + 4 * tid;
       const int32_t s = t >> kGridTwShift, cc = t & (kGridTw - 1);
