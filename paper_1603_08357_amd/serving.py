@@ -232,10 +232,24 @@ class Scheduler:
                 jobs[i].arrival = t0 + jobs[i].arrival
                 self.submit(jobs[i])
                 i += 1
-            self.poll()
+            if not self.poll() and self.running:
+                time.sleep(0)  # lets the executor's copy threads take the interpreter lock
             if idle_wait and self.idle and i < len(jobs):
                 time.sleep(min(idle_wait, max(0.0, t0 + jobs[i].arrival - self.clock())))
         return self.finished
+
+
+class _Done:
+    """An already finished copy (the Future interface the executor uses)."""
+
+    def __init__(self, value):
+        self.value = value
+
+    def done(self) -> bool:
+        return True
+
+    def result(self):
+        return self.value
 
 
 class GpuExecutor:
@@ -247,7 +261,8 @@ class GpuExecutor:
 
     def __init__(self, n_streams: int = 4, device=None, max_sites: int = 1 << 24,
                  tick_sites: int = 1 << 17, tick_jobs: int = 512, tick_total_sites: int = 1 << 23,
-                 tick_total_bonds: int = 1 << 25, tuning=None, copy_threads: int = 8):
+                 tick_total_bonds: int = 1 << 25, tuning=None, copy_threads: int = 8,
+                 inline_copy_sites: int = 1 << 20):
         import torch
         import paper_1603_08357_amd as ccl
         self.torch, self.ccl = torch, ccl
@@ -266,6 +281,7 @@ class GpuExecutor:
         # loop keeps admitting while they are copied
         import concurrent.futures as cf
         self._copiers = cf.ThreadPoolExecutor(max_workers=copy_threads)
+        self.inline_copy_sites = inline_copy_sites
         if tick_sites > 0:  # the capacity plans up front: creating one synchronizes the device
             for i in range(n_streams):
                 self._plan(i)
@@ -373,14 +389,18 @@ class GpuExecutor:
 
     def done(self, h) -> bool:
         """True once the launch's labels are in host memory: when its last
-        event has completed, the copy out of the pinned buffer is handed to
-        a host thread, and the launch is done when that copy is."""
+        event has completed, labels of up to `inline_copy_sites` sites are
+        copied out of the pinned buffer at once, larger ones on a host thread,
+        and the launch is done when that copy is."""
         st = h[6]
         if st["copy"] is None:
             if not h[1][3].query():
                 return False
-            jobs, _, _, (pin, host), site_off = h[0], h[1], h[2], h[3], h[4]
-            st["copy"] = self._copiers.submit(self._copy_out, host, site_off, len(jobs))
+            jobs, (pin, host), site_off = h[0], h[3], h[4]
+            if host.numel() <= self.inline_copy_sites:
+                st["copy"] = _Done(self._copy_out(host, site_off, len(jobs)))
+            else:
+                st["copy"] = self._copiers.submit(self._copy_out, host, site_off, len(jobs))
         return st["copy"].done()
 
     def finish(self, h):
