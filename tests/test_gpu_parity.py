@@ -845,7 +845,7 @@ def test_serving_ticks_under_a_binding_budget(ccl):
         assert j.t_kernel_ms >= 0 and j.t_h2d_ms >= 0
 
 
-@pytest.mark.parametrize("schedule", [3, 2])
+@pytest.mark.parametrize("schedule", [3, 2, 1])
 def test_capacity_plan_takes_a_layout_per_launch(ccl, schedule):
     """One capacity plan, five layouts set and launched back to back on one
     stream with no synchronization in between (each layout's tables are
