@@ -1001,12 +1001,24 @@ def main():
             del gp, outp
             torch.cuda.empty_cache()
 
+    def cpu_oracle_edges(g, reps=5):
+        """The oracle on one core, median of `reps` labelings (ms)."""
+        import oracle
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.label_edges(g.n_sites, g.src, g.dst, g.occ)
+            times.append(time.perf_counter() - t0)
+        return {"ms": round(1e3 * float(np.median(times)), 3), "cores": 1, "kind": "oracle",
+                "sample": f"the same realization, median of {reps} labelings"}
+
     def do_honeycomb():
         h = gen.honeycomb_realization(256, 0.6527, 1)
         _, rh = bench_edges(h, max(args.steps, 50), args.warmup)
         extra["honeycomb_L256"] = {"Gsites_s": round(rh["n"] / (rh["ms"] * 1e-3) / 1e9, 3),
                                    "ms_per_step": round(rh["ms"], 5),
-                                   "kernels": {k: round(v["mean_ms"], 5) for k, v in rh["kernels"].items()}}
+                                   "kernels": {k: round(v["mean_ms"], 5) for k, v in rh["kernels"].items()},
+                                   "cpu_oracle": cpu_oracle_edges(h)}
 
     def do_random3reg():
         ceil = extra.get("probe_random_access")
@@ -1021,6 +1033,8 @@ def main():
                    "warm_step_ms": rb["warm_step_ms"], "cold_step_ms": rb["cold_step_ms"],
                    "kernels": {k: round(v["mean_ms"], 5) for k, v in rb["kernels"].items()},
                    "random_access_roofline": random_access_roofline(b, rb, ceil)}
+            if pp == 0.5:
+                row["cpu_oracle"] = cpu_oracle_edges(b)
             extra[f"random3reg_2^24_p{pp}"] = row
             if pp == 0.5:
                 try:
