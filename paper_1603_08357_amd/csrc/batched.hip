@@ -258,8 +258,10 @@ __global__ void k_batched(BatchArgs a) {
           for (int k = 0; k < K; ++k) {
             if (!need[k]) continue;
             const int32_t i = i0 + k * (int32_t)blockDim.x + (int32_t)threadIdx.x;
-            if (x[k] != q[k]) lab_st(lab + p[k], x[k]);
-            lab_st(lab + i, x[k]);
+            // final roots, which no later kernel of the call writes or updates:
+            // plain stores (device-scope ones cost 0.37 ms on the 4096-instance batch)
+            if (x[k] != q[k]) lab[p[k]] = x[k];
+            lab[i] = x[k];
           }
           if (__any(bad)) break;
         }

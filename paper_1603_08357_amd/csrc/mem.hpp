@@ -14,7 +14,8 @@
 // goes through these helpers.  Measured cost on MI355X: none for the
 // edge-list init and flatten, 0.011 ms for the tile kernel of the 2^26-site
 // lattice.  The plain stores left are a call's final values that no later
-// kernel of the call touches (the windowed CSR flatten).
+// kernel of the call touches (the windowed CSR flatten, the batched FLATTEN
+// items).
 #pragma once
 
 #include <hip/hip_runtime.h>
