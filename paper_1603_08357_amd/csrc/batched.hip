@@ -461,8 +461,50 @@ __global__ void __launch_bounds__(kBatchBlock, kBatchTilesPerCu) k_batched_tile(
   }
   drain_joins(par, stage[wave], staged);
   __syncthreads();
-  // the tile's labels (instance-local): each site's tile-local root
-  for (int32_t t = tid; t < cnt; t += kBatchBlock) st_dev(lab + lo + t, lo + lds16_find(par, t));
+  // the tile's labels (instance-local): each site's tile-local root.  A
+  // pass takes two runs of 4 kBatchBlock consecutive sites, four per lane,
+  // all eight chases in lockstep rounds; 16-byte device-scope stores when
+  // the tile's labels are 16-byte aligned
+  {
+    constexpr int32_t kRun = 4 * kBatchBlock;
+    const int32_t n_runs = (cnt + kRun - 1) / kRun;
+    const bool vec = (reinterpret_cast<uintptr_t>(lab + lo) & 15) == 0;
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(lab + lo, vec ? (uint32_t)cnt * 4u : 0u);
+    for (int32_t q0 = 0; q0 < n_runs; q0 += 2) {
+      int32_t x[8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t t0 = min(q0 + h, n_runs - 1) * kRun + 4 * tid;  // a missing run repeats the last
+        const int32_t t = t0 < cnt ? t0 : 0;                          // past the tile: slot 0
+        const uint2 wv = reinterpret_cast<const uint2*>(par)[t >> 2];
+        x[4 * h + 0] = (int32_t)(wv.x & 0xFFFFu);
+        x[4 * h + 1] = (int32_t)(wv.x >> 16);
+        x[4 * h + 2] = (int32_t)(wv.y & 0xFFFFu);
+        x[4 * h + 3] = (int32_t)(wv.y >> 16);
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int32_t p = lds16_ld(par + x[k]);
+        if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t t = (q0 + h) * kRun + 4 * tid;
+        if (q0 + h >= n_runs || t >= cnt) continue;
+        if (vec && t + 4 <= cnt) {
+          st_dev4(rl, 4u * (uint32_t)t, make_int4(lo + x[4 * h], lo + x[4 * h + 1], lo + x[4 * h + 2], lo + x[4 * h + 3]));
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (t + k < cnt) st_dev(lab + lo + t + k, lo + x[4 * h + k]);
+        }
+      }
+    }
+  }
   if (tid == 0)
     st_dev(a.counts + blockIdx.x, n_out > (uint32_t)kTilePairs ? -1 : (int32_t)n_out);
 }
