@@ -112,6 +112,18 @@ def test_plan_argument_errors(lib):
     assert lib.ccl_plan_set_layout(None, 2, so, bo, None) == INVALID
 
 
+def test_probe_argument_errors(lib):
+    INVALID = 1
+    P = ctypes.c_void_p
+    lib.ccl_probe_random.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P, P]
+    assert lib.ccl_probe_random(None, 16, 16, 0, P(64), None) == INVALID
+    assert lib.ccl_probe_random(P(64), 0, 16, 0, P(128), None) == INVALID
+    assert lib.ccl_probe_random(P(64), 1 << 31, 16, 0, P(128), None) == INVALID
+    assert lib.ccl_probe_random(P(64), 16, -1, 0, P(128), None) == INVALID
+    assert lib.ccl_probe_random(P(64), 16, 16, 5, P(128), None) == INVALID
+    assert lib.ccl_probe_random(P(64), 16, 16, 0, None, None) == INVALID
+
+
 def test_validation_argument_errors(lib):
     INVALID = 1
     bad = ctypes.c_int64()

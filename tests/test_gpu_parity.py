@@ -1043,3 +1043,31 @@ def test_batched_tiled_any_bond_order(ccl, small_sites):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), oracle.label_batched(site_off, bond_off, src, dst, None))
     plan.close()
+
+
+def test_probes_stay_in_bounds_and_do_their_work(ccl):
+    """The copy probe copies; the random-access probe's fill mode writes only
+    in-range indices (its dependent-chase mode follows them), and its
+    atomicMin mode lowers entries to op numbers below n_ops."""
+    n = 1 << 20
+    src = torch.arange(3 * n, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    ccl.probe_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    table = torch.empty(n, dtype=torch.int32, device="cuda")
+    ccl.probe_random(table, 0, 4)  # fill: table[i] is a pseudo-random index in [0, n)
+    torch.cuda.synchronize()
+    t = table.cpu().numpy()
+    assert t.min() >= 0 and t.max() < n and len(np.unique(t)) > n // 2
+    for mode in (0, 3):  # gather, dependent chase: read only
+        ccl.probe_random(table, 8 * n, mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(table.cpu().numpy(), t)
+    table.fill_(2**31 - 1)
+    ops = 4 * n
+    ccl.probe_random(table, ops, 1)  # atomicMin with the op number
+    torch.cuda.synchronize()
+    t = table.cpu().numpy()
+    hit = t != 2**31 - 1
+    assert hit.sum() > n // 2 and t[hit].max() < ops and t[hit].min() >= 0
