@@ -7,7 +7,9 @@
 //      Algorithm 1 on LDS, its atomicMin a 32-bit compare-and-swap -- for every
 //      occupied bond whose two ends lie in the tile, a root chase in LDS, and
 //      one coalesced store of the tile's labels (each site's tile-local root,
-//      the tile's minimum member of its local cluster).  Occupied bonds that
+//      the tile's minimum member of its local cluster; the grid tiles store
+//      a near ancestor for the rare site deeper than their lockstep chase
+//      reaches).  Occupied bonds that
 //      leave the tile are appended, as (site, neighbour) pairs, to the tile's
 //      own segment of the workspace (the segment has room for every bond of
 //      the tile, so no global counter is needed);
@@ -372,7 +374,7 @@ constexpr int kGridTh = kCsrTile / kGridTw;
 static_assert(kGridTh <= 64, "one lane per tile row in the header loads");
 static_assert(kGridTw >= kTileBlock && (4 * kTileBlock) % kGridTw == 0, "the epilogue's runs cover whole rows");
 constexpr int kEpiRuns = 2;    // runs of 4 kTileBlock slots per epilogue pass
-constexpr int kEpiRounds = 3;  // lockstep LDS rounds before the fallback chases
+constexpr int kEpiRounds = 3;  // lockstep LDS rounds of the epilogue's chases
 
 struct GridGeo {
   int64_t n;        // sites
@@ -688,10 +690,14 @@ __global__ void __launch_bounds__(kTileBlock)
     }
   }
   __syncthreads();
-  // the tile's labels: each site's tile-local root.  A pass takes kEpiRuns
-  // runs of 4 kTileBlock consecutive slots, four per lane (a run covers whole
-  // tile rows), all their chases resolved together; 16-byte stores when the
-  // label array and the row length allow it
+  // the tile's labels: each site's ancestor kEpiRounds + 1 links up its
+  // tile-local tree -- its tile-local root for all but the rare deeper
+  // chains, which the cross kernel and the flatten finish in global memory
+  // (a check for them and a divergent chase to the root cost more here than
+  // the few extra global steps they cause).  A pass takes kEpiRuns runs of
+  // 4 kTileBlock consecutive slots, four per lane (a run covers whole tile
+  // rows), all their chases in lockstep; 16-byte stores when the label array
+  // and the row length allow it
   const bool vec = ((reinterpret_cast<uintptr_t>(label + u0) & 15) == 0) && (geo.w % 4 == 0);
   const __amdgpu_buffer_rsrc_t rl = make_rsrc(label + u0, vec && fast ? (uint32_t)span_sites * 4u : 0u);
   auto gid = [&](int32_t t) {
@@ -715,11 +721,6 @@ __global__ void __launch_bounds__(kTileBlock)
     for (int r = 0; r < kEpiRounds; ++r)
 #pragma unroll
       for (int k = 0; k < 4 * E; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
-#pragma unroll
-    for (int k = 0; k < 4 * E; ++k) {
-      const int32_t p = lds16_ld(par + x[k]);
-      if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
-    }
 #pragma unroll
     for (int h = 0; h < E; ++h) {
       if (q0 + h >= n_runs) continue;
@@ -746,8 +747,8 @@ __global__ void __launch_bounds__(kTileBlock)
 // those joins touch) walks the tile's leaving-bond pairs in chunks.  Before
 // anything touches global atomics, a chunk is reduced in LDS:
 //   1. every pair (u, v) is replaced by (label[u], label[v]) -- after the
-//      tile kernel these are tile-local roots, so many pairs coincide (a
-//      cluster crosses a tile boundary at many bonds);
+//      tile kernel these are (nearly always) tile-local roots, so many pairs
+//      coincide (a cluster crosses a tile boundary at many bonds);
 //   2. those labels are entered in a hash table (open addressing; a chunk of
 //      kCrossChunk pairs has at most 2 kCrossChunk distinct labels, so the
 //      table of kCrossSlots never fills), and the pairs are joined there with
@@ -890,7 +891,7 @@ __global__ void __launch_bounds__(kCrossBlock)
 
 // Step (iv) for the CSR path: one workgroup per window of kFlatWin sites,
 // staged in LDS with 16-byte loads.  After the tile and cross kernels a
-// site's label is its tile-local root, usually inside the same window, so
+// site's label is (nearly always) its tile-local root, often inside the same window, so
 // the parent's label is an LDS read; only parents whose cluster was joined
 // across tiles need a chase in global memory, and its result is cached in
 // the window (every thread sharing that parent then finds the root in LDS).
@@ -1055,7 +1056,7 @@ ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, c
     CCL_LAUNCH("ccl_csr_tile", k_csr_tile<kOccAll>, (unsigned)n_tiles, kTileBlock, 0, s, n,
                row_ptr, col, occ, label, pairs, seg, rng);
   }
-  if (n_tiles == 1) return CCL_OK;
+  if (n_tiles == 1 && !grid) return CCL_OK;  // one slab tile's labels are final (a grid has >= 2 tiles)
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)(n_tiles * kCrossSplit), kCrossBlock, 0, s, pairs, seg,
              label);
   if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
