@@ -464,8 +464,13 @@ __global__ void __launch_bounds__(kBatchBlock, kBatchTilesPerCu) k_batched_tile(
   // the tile's labels (instance-local): each site's tile-local root.  A
   // pass takes two runs of 4 kBatchBlock consecutive sites, four per lane,
   // all eight chases in lockstep rounds; 16-byte device-scope stores when
-  // the tile's labels are 16-byte aligned
+  // the tile's labels are 16-byte aligned.  In an instance of several tiles
+  // a site deeper than six links keeps the ancestor the lockstep rounds
+  // reached, which the leaving-bond joins and the flatten follow (a check
+  // and a divergent chase to the root there cost 1.3 ms of the 4096-instance
+  // batch's tile kernel and saved 1.0 ms of its flatten).
   {
+    const bool single = n <= kBatchTile;
     constexpr int32_t kRun = 4 * kBatchBlock;
     const int32_t n_runs = (cnt + kRun - 1) / kRun;
     const bool vec = (reinterpret_cast<uintptr_t>(lab + lo) & 15) == 0;
@@ -486,10 +491,17 @@ __global__ void __launch_bounds__(kBatchBlock, kBatchTilesPerCu) k_batched_tile(
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);  // a root reads itself
+      if (single) {  // an instance of one tile has no later kernel: its labels must be roots
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int32_t p = lds16_ld(par + x[k]);
-        if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
+        for (int k = 0; k < 8; ++k) {
+          const int32_t p = lds16_ld(par + x[k]);
+          if (p != x[k]) x[k] = lds16_find(par, x[k]);  // the rare longer chain
+        }
+      } else {  // two more lockstep rounds (fewer left to the flatten; measured best)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) x[k] = lds16_ld(par + x[k]);
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
