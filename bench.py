@@ -159,6 +159,19 @@ def ingest_counters(fetch_csv: str, write_csv: str, workload: str) -> dict:
 
 # ---------------------------------------------------------------- timing
 
+_WORK_STREAM = []
+
+
+def work_stream():
+    """A stream of its own for the timed labelings (launches on the legacy
+    default stream carry its implicit synchronization: 0.012-0.02 ms per
+    three-kernel step on MI355X)."""
+    import torch
+    if not _WORK_STREAM:
+        _WORK_STREAM.append(torch.cuda.Stream())
+    return _WORK_STREAM[0]
+
+
 def time_steps(fn, steps: int, warmup: int, stream):
     import torch
     for _ in range(warmup):
@@ -197,10 +210,16 @@ def step_distribution(fn, steps: int, stream, before=None):
 
 
 def make_flush(nbytes=1 << 30):
-    """A 1 GiB device write that evicts the labels from L2 and the MALL."""
+    """A 1 GiB device write that evicts the labels from L2 and the MALL,
+    enqueued on the timed labelings' stream (so it ends before a step starts)."""
     import torch
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    return lambda: buf.fill_(1)
+    torch.cuda.synchronize()
+
+    def flush():
+        with torch.cuda.stream(work_stream()):
+            buf.fill_(1)
+    return flush
 
 
 def host_info():
@@ -261,11 +280,13 @@ def bench_csr(L, p, seed, steps, warmup, grid_width=0):
     occ = torch.from_numpy(g.occ).cuda()
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     ws = torch.empty(max(ccl.csr_workspace_bytes(n, m), 8), dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()  # the inputs are resident before the first step
+    stream = work_stream()
     fn = lambda: ccl.label_csr(rp, col, occ, out=out, workspace=ws, stream=stream, grid_width=grid_width)
     ms, wall = time_steps(fn, steps, warmup, stream)
     kern = traced_kernels(fn, steps)
     dist = step_distribution(fn, steps, stream)
+    torch.cuda.synchronize()  # the labels are read on other streams afterwards
     return g, out, dict(n=n, m=m, ms=ms, wall=wall, kernels=kern, step_ms=dist)
 
 
@@ -276,15 +297,17 @@ def bench_edges(g, steps, warmup, cold=False):
     dst = torch.from_numpy(g.dst).cuda()
     occ = torch.from_numpy(g.occ).cuda()
     out = torch.empty(g.n_sites, dtype=torch.int32, device="cuda")
-    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()  # the inputs are resident before the first step
+    stream = work_stream()
     fn = lambda: ccl.label(src, dst, g.n_sites, occ, out=out, stream=stream)
     ms, wall = time_steps(fn, steps, warmup, stream)
-    kern = traced_kernels(fn, steps)
+    kern = traced_kernels(fn, steps)  # ends with a device synchronization
     res = dict(n=g.n_sites, m=len(g.src), ms=ms, kernels=kern,
                n_clusters=int((out == torch.arange(g.n_sites, dtype=torch.int32, device="cuda")).sum().item()))
     if cold:  # warm: back to back; cold: a 1 GiB write ahead of every step
         res["warm_step_ms"] = step_distribution(fn, steps, stream)
         res["cold_step_ms"] = step_distribution(fn, steps, stream, before=make_flush())
+        torch.cuda.synchronize()
         torch.cuda.empty_cache()
     return out, res
 
