@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(kCrossBlock)
 // the scattered parent stores.
 constexpr int kFlatWin = 16384;
 constexpr int kFlatBlock = 1024;
-constexpr int kFlatPer = 8;  // sites a lane resolves in lockstep
+constexpr int kFlatPer = 4;  // sites a lane resolves in lockstep (2, 6, 8, 16 measured slower)
 
 __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, int64_t n) {
   __shared__ int32_t w[kFlatWin];
