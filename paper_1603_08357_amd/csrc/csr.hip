@@ -31,7 +31,7 @@ constexpr int kTileShift = 16;
 constexpr int kRowsPerThread = 4;  // rows per thread per iteration (row path)
 constexpr int kDegFast = 4;        // bonds per row kept in registers (row path)
 constexpr int kChunkRows = kTileBlock * kRowsPerThread;
-constexpr int kGroupsPerIter = 3;  // groups of four bonds per lane per step (affine path)
+constexpr int kGroupsPerIter = 2;  // groups of four bonds per lane per step (affine path; 1, 3, 4 measured slower)
 constexpr int kLeaveBits = 5;  // a lane leaves at most 16 bonds per step: 5-bit counts
 static_assert(4 * kGroupsPerIter < (1 << kLeaveBits) && kRowsPerThread * kDegFast < (1 << kLeaveBits),
               "a lane's leaving bonds per step must fit a count of kLeaveBits bits");
