@@ -52,7 +52,7 @@ def alg_bytes_csr(kernel: str, n: int, m: int) -> float:
         return 4.0 * (n + 1) + 5.0 * m + 4.0 * n
     if kernel == "ccl_csr_cross":  # nothing the method itself must move
         return 0.0
-    if kernel in ("ccl_flatten", "ccl_flatten_window"):  # labels read and written
+    if kernel in ("ccl_flatten", "ccl_flatten_window", "ccl_flatten_grid"):  # labels read and written
         return 8.0 * n
     return 0.0
 
@@ -112,6 +112,7 @@ KERNEL_NAMES = {"k_csr_tile": "ccl_csr_tile", "k_csr_tile_grid": "ccl_csr_tile",
                 "k_ell_init": "ccl_ell_init", "k_ell_reduce": "ccl_ell_reduce",
                 "k_sizes_own": "ccl_sizes_own", "k_sizes_foreign": "ccl_sizes_foreign",
                 "k_flatten": "ccl_flatten", "k_flatten_window": "ccl_flatten_window",
+                "k_flatten_grid": "ccl_flatten_grid",
                 "k_init": "ccl_init", "k_merge_edges": "ccl_merge_edges"}
 
 

@@ -978,6 +978,210 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten_window(int32_t* label, i
   for (int32_t t = 4 * cnt4 + tid; t < cnt; t += kFlatBlock) label[w0 + t] = w[t];
 }
 
+// Step (iv) for grid tiles.  After the tile and cross kernels a site's label
+// is (nearly always) its tile-local root: the smallest id of its cluster
+// inside its grid tile, so a site of the same tile rows or above and, for
+// nearly every cluster, only a few hundred columns away.  A window of the full
+// tile height (kGridTh rows) by kFlatCols columns, aligned with the tiles,
+// therefore holds the parent of nearly every one of its sites (97% on the
+// triangle lattice at p_c with 512 columns, against 22% for a window of two
+// whole rows of 8192 sites).  One workgroup per window; a lane owns four
+// 16-byte groups of a row (16 slots):
+//   load     the groups into LDS; the lane notes its slots whose label lies
+//            outside the window (a tile root joined across tiles, a parent
+//            further away);
+//   phase 1  without waiting for the other lanes, those slots are chased to
+//            their roots in global memory, kFlatChase chases per lane in
+//            flight, and marked final in LDS (bit 31: labels are below
+//            2^31 - 1);
+//   phase 2  every group is read back from LDS and each slot resolved:
+//            marked, a root, or its parent's slot read -- after phase 1 an
+//            unmarked label always lies inside the window, so this follows
+//            labels in LDS only -- and the group goes to global memory at
+//            once with a 16-byte store.
+// Per slot this is a few LDS accesses and a dozen VALU operations; what the
+// streaming passes do not hide is the latency of the phase-1 chases through
+// the forest of joined tile roots.  The final values are plain stores, for
+// the same reason as the windowed flatten above: no later kernel of the call
+// touches these words.  On the 2^26-site triangle lattice this kernel takes
+// 0.156 ms against 0.170 ms for the windowed flatten (0.107 ms with the two
+// phases left out, 0.113 ms with phase 1 alone left out); 256-column
+// windows of 512 or 256 lanes measured 0.185 / 0.255 ms.
+constexpr int kFlatColsShift = 9;
+constexpr int kFlatGridBlock = 1024;
+constexpr int kFlatCols = 1 << kFlatColsShift;
+constexpr int kFlatSlots = kGridTh * kFlatCols;
+constexpr int kFlatGroups = kFlatSlots / (4 * kFlatGridBlock);  // 16-byte groups of one lane
+constexpr int kFlatChase = 2;                                // global chases a lane keeps in flight (1, 4, 8 measured slower)
+constexpr int32_t kFinal = INT32_MIN;                        // LDS mark: the slot holds its final root
+static_assert(kGridTw % kFlatCols == 0, "windows must not straddle grid tiles");
+static_assert(kFlatSlots % (4 * kFlatGridBlock) == 0 && 4 * kFlatGroups <= 32 && kFlatGroups % 2 == 0,
+              "whole 16-byte groups per lane, pending slots in a 32-bit mask, groups in pairs");
+
+template <bool POW2>
+__global__ void __launch_bounds__(kFlatGridBlock) k_flatten_grid(int32_t* label, GridGeo geo, int32_t wins_x) {
+  __shared__ int32_t w[kFlatSlots];
+  const int tid = threadIdx.x;
+  const int32_t b = (int32_t)xcd_block_id();
+  const int32_t wy = b / wins_x, wx = b - wy * wins_x;
+  const int64_t base64 = (int64_t)wy * kGridTh * geo.w + (int64_t)wx * kFlatCols;
+  if (base64 >= geo.n) return;  // the partial last row ends left of this window: no site
+  const uint32_t n = (uint32_t)geo.n;
+  const uint32_t w32 = (uint32_t)geo.w;  // w < n <= 2^31 - 1
+  const uint32_t rows = (uint32_t)min((int64_t)kGridTh, geo.h - (int64_t)wy * kGridTh);
+  const uint32_t cw = min((uint32_t)kFlatCols, w32 - (uint32_t)wx * kFlatCols);  // a multiple of 4, as w is
+  const uint32_t base = (uint32_t)base64;
+  const uint32_t lim = rows * w32;  // <= kGridTh w < 2^32
+
+  // Slot of site v, or -1 when v lies outside the window.  POW2: bit fields;
+  // otherwise a float quotient corrected by one step (the row within reach
+  // is below kGridTh).
+  auto slot_of = [&](int32_t v) -> int32_t {
+    const uint32_t d = (uint32_t)v - base;  // wraps to >= lim when v < base
+    if (d >= lim) return -1;
+    uint32_t r, c;
+    if (POW2) {
+      r = d >> geo.w_shift;
+      c = d & (w32 - 1u);
+    } else {
+      int32_t q = (int32_t)((float)d * geo.inv_w);
+      int32_t e = (int32_t)d - q * (int32_t)w32;
+      if (e < 0) {
+        --q;
+        e += (int32_t)w32;
+      } else if (e >= (int32_t)w32) {
+        ++q;
+        e -= (int32_t)w32;
+      }
+      r = (uint32_t)q;
+      c = (uint32_t)e;
+    }
+    return c < cw ? (int32_t)((r << kFlatColsShift) | c) : -1;
+  };
+
+  // The lane's groups: group i is slots 4 (tid + i kFlatGridBlock) + 0..3, in
+  // window row (tid >> 7) + 8 i, columns 4 (tid & 127) + 0..3.
+  const uint32_t c0 = (uint32_t)(tid & (kFlatCols / 4 - 1)) * 4u;
+  const uint32_t r0 = (uint32_t)tid / (kFlatCols / 4);
+  constexpr uint32_t kRowStep = kFlatGridBlock / (kFlatCols / 4);
+  auto gsite = [&](int i) { return base + (r0 + kRowStep * i) * w32 + c0; };  // < 2^32: rows * w < n + w
+  auto gvalid = [&](int i) { return r0 + kRowStep * i < rows && c0 < cw && gsite(i) < n; };
+  auto gslot = [&](int i) { return 4 * (tid + i * kFlatGridBlock); };
+
+  // ---- load
+  uint32_t pend = 0;  // bit 4 i + j: slot j of group i needs a chase in global memory
+#pragma unroll
+  for (int i = 0; i < kFlatGroups; ++i) {
+    if (!gvalid(i)) continue;
+    const uint32_t g = gsite(i);
+    int4 v;
+    if (g + 4u <= n) {
+      v = *reinterpret_cast<const int4*>(label + g);
+    } else {  // the end of the last row
+      v.x = label[g];
+      v.y = g + 1u < n ? label[g + 1u] : (int32_t)g + 1;
+      v.z = g + 2u < n ? label[g + 2u] : (int32_t)g + 2;
+      v.w = g + 3u < n ? label[g + 3u] : (int32_t)g + 3;
+    }
+    *reinterpret_cast<int4*>(w + gslot(i)) = v;
+    const int32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (g + (uint32_t)j < n && slot_of(vv[j]) < 0) pend |= 1u << (4 * i + j);
+  }
+
+  // ---- phase 1: labels outside the window, chased in global memory.  A
+  // lane reads and marks only its own slots, so it starts as soon as its own
+  // loads are in LDS.  A chase that took more than one step also stores the
+  // root it found at the label it started from (a site outside the window,
+  // usually a tile root): windows that reach that site later find the root
+  // in one step.  Like the window's own stores this is a final value.
+  {
+    int32_t cs[kFlatChase], cx[kFlatChase], c0[kFlatChase], c1[kFlatChase];
+#pragma unroll
+    for (int c = 0; c < kFlatChase; ++c) cs[c] = -1;
+    for (;;) {
+      bool busy = false;
+#pragma unroll
+      for (int c = 0; c < kFlatChase; ++c) {
+        if (cs[c] < 0 && pend != 0) {
+          const int k = __builtin_ctz(pend);
+          pend &= pend - 1u;
+          cs[c] = gslot(k >> 2) + (k & 3);
+          cx[c] = lds_ld(w + cs[c]);
+          c0[c] = cx[c];  // where the chase starts
+          c1[c] = cx[c];  // its label, once read
+        }
+        busy = busy || cs[c] >= 0;
+      }
+      if (!__any(busy)) break;
+      int32_t cy[kFlatChase];
+#pragma unroll
+      for (int c = 0; c < kFlatChase; ++c) cy[c] = lab_ld(label + (cs[c] >= 0 ? cx[c] : 0));
+#pragma unroll
+      for (int c = 0; c < kFlatChase; ++c) {
+        const bool root = cs[c] >= 0 && cy[c] == cx[c];
+        if (root) lds_st(w + cs[c], cx[c] | kFinal);
+        if (root && c1[c] != cx[c]) label[c0[c]] = cx[c];
+        c1[c] = cs[c] >= 0 && c1[c] == c0[c] ? cy[c] : c1[c];
+        cx[c] = cs[c] >= 0 ? cy[c] : cx[c];
+        cs[c] = root ? -1 : cs[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: the other slots, in LDS; each group stored when resolved
+#pragma unroll
+  for (int i0 = 0; i0 < kFlatGroups; i0 += 2) {
+    int32_t v[8], y[8], ps[8];
+    bool todo[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int4 t = gvalid(i0 + h) ? *reinterpret_cast<const int4*>(w + gslot(i0 + h)) : int4{-1, -1, -1, -1};
+      v[4 * h] = t.x;
+      v[4 * h + 1] = t.y;
+      v[4 * h + 2] = t.z;
+      v[4 * h + 3] = t.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t id = (int32_t)(gsite(i0 + (k >> 2)) + (uint32_t)(k & 3));
+      todo[k] = v[k] >= 0 && v[k] != id;  // not marked, not a root
+      ps[k] = todo[k] ? slot_of(v[k]) : 0;  // inside the window: unmarked labels are, after phase 1
+      y[k] = lds_ld(w + ps[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (!todo[k]) continue;
+      int32_t x = v[k], yy = y[k];
+      if (yy >= 0 && yy != x) {  // the parent is neither marked nor a root: follow on
+        do {
+          x = yy;
+          yy = lds_ld(w + slot_of(x));
+        } while (yy >= 0 && yy != x);
+        // for the sites that share this parent
+        lds_st(w + ps[k], (yy < 0 ? yy : x) | kFinal);
+      }
+      v[k] = yy < 0 ? yy : x;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!gvalid(i0 + h)) continue;
+      const uint32_t g = gsite(i0 + h);
+      const int4 t{v[4 * h] & INT32_MAX, v[4 * h + 1] & INT32_MAX, v[4 * h + 2] & INT32_MAX,
+                   v[4 * h + 3] & INT32_MAX};
+      if (g + 4u <= n) {
+        *reinterpret_cast<int4*>(label + g) = t;
+      } else {
+        label[g] = t.x;
+        if (g + 1u < n) label[g + 1u] = t.y;
+        if (g + 2u < n) label[g + 2u] = t.z;
+      }
+    }
+  }
+}
+
 // Tiles of the id grid of row length w: grid tiles when the rows are longer
 // than a grid tile, w is a multiple of 4 and there are at least kGridTh rows,
 // else slabs of kCsrTile consecutive ids (w <= 0: no grid).
@@ -1020,8 +1224,8 @@ ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, c
     pairs = reinterpret_cast<int2*>(static_cast<char*>(workspace) + csr_seg_bytes(n));
   }
   const PhiloxOcc rng = draw != nullptr ? *draw : PhiloxOcc{0, 0, 0};
+  GridGeo geo{};
   if (grid) {
-    GridGeo geo;
     geo.n = n;
     geo.w = grid_w;
     geo.h = (n + grid_w - 1) / grid_w;
@@ -1029,6 +1233,8 @@ ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, c
     geo.inv_w = 1.0f / (float)grid_w;
     geo.w_shift = 0;
     while (((int64_t)1 << geo.w_shift) < grid_w) ++geo.w_shift;
+  }
+  if (grid) {
     const bool pow2 = ((int64_t)1 << geo.w_shift) == grid_w;
 #define CCL_GRID_TILE(OCC)                                                                      \
   do {                                                                                          \
@@ -1060,6 +1266,15 @@ ccl_status launch_label_csr(int64_t n, int64_t grid_w, const int32_t* row_ptr, c
   CCL_LAUNCH("ccl_csr_cross", k_csr_cross, (unsigned)(n_tiles * kCrossSplit), kCrossBlock, 0, s, pairs, seg,
              label);
   if ((reinterpret_cast<uintptr_t>(label) & 15) != 0) return launch_flatten(n, label, s, d);
+  if (grid) {
+    const int32_t wins_x = (int32_t)((grid_w + kFlatCols - 1) / kFlatCols);
+    const int64_t n_win = ((geo.h + kGridTh - 1) / kGridTh) * wins_x;
+    if (((int64_t)1 << geo.w_shift) == grid_w)
+      CCL_LAUNCH("ccl_flatten_grid", k_flatten_grid<true>, (unsigned)n_win, kFlatGridBlock, 0, s, label, geo, wins_x);
+    else
+      CCL_LAUNCH("ccl_flatten_grid", k_flatten_grid<false>, (unsigned)n_win, kFlatGridBlock, 0, s, label, geo, wins_x);
+    return CCL_OK;
+  }
   const unsigned n_win = (unsigned)((n + kFlatWin - 1) / kFlatWin);
   CCL_LAUNCH("ccl_flatten_window", k_flatten_window, n_win, kFlatBlock, 0, s, label, n);
   return CCL_OK;
