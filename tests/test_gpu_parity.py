@@ -193,13 +193,17 @@ def rect_triangle_csr(w, h, n=None):
 
 
 @pytest.mark.parametrize("w,h,cut", [(8192, 40, 0), (8192, 40, 8192 - 100), (6004, 33, 0), (6004, 33, 5),
-                                     (12288, 36, 0), (4100, 37, 4100), (2052, 70, 0), (4104, 96, 0)])
+                                     (12288, 36, 0), (4100, 37, 4100), (2052, 70, 0), (4104, 96, 0),
+                                     (8192, 33, 8192 - 100)])
 def test_csr_grid_tiles(ccl, w, h, cut):
     """Grid tiles (32 rows x 2048 columns) on rectangular lattices: ragged
     tile columns (w not a multiple of 2048) and tile rows (h not a multiple of
     32), a partial last grid row whose missing sites make the last rows
     non-affine (the row path), a tile with no site, no mask, a device-drawn
-    mask, and an occupancy view one byte off 4-byte alignment."""
+    mask, and an occupancy view one byte off 4-byte alignment.  The flatten's
+    32 x 512 windows are ragged the same way (w not a multiple of 512), and
+    with h = 33 and a last row of 100 sites most windows of the last window
+    row hold no site at all."""
     n = w * h - cut
     row_ptr, col = rect_triangle_csr(w, h, n)
     occ = gen.bernoulli(w + h, len(col), 0.3473)
@@ -216,6 +220,13 @@ def test_csr_grid_tiles(ccl, w, h, cut):
     out = ccl.label_csr(dev(row_ptr), dev(col), buf[1:], grid_width=w)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), want)
+    # labels written through a view 4 bytes off 16-byte alignment (the
+    # flatten then takes its per-site form instead of the 16-byte windows)
+    lab = torch.full((n + 1,), -1, dtype=torch.int32, device="cuda")
+    ccl.label_csr(dev(row_ptr), dev(col), dev(occ), out=lab[1:], grid_width=w)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lab[1:].cpu().numpy(), want)
+    assert int(lab[0].item()) == -1
 
 
 def test_csr_grid_any_graph(ccl):
