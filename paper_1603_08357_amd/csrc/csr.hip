@@ -1060,7 +1060,8 @@ __global__ void __launch_bounds__(kFlatGridBlock) k_flatten_grid(int32_t* label,
   };
 
   // The lane's groups: group i is slots 4 (tid + i kFlatGridBlock) + 0..3, in
-  // window row (tid >> 7) + 8 i, columns 4 (tid & 127) + 0..3.
+  // window row r0 + kRowStep i, columns c0 + 0..3 (with 512 columns and 1024
+  // lanes: row (tid >> 7) + 8 i, columns 4 (tid & 127) + 0..3).
   const uint32_t c0 = (uint32_t)(tid & (kFlatCols / 4 - 1)) * 4u;
   const uint32_t r0 = (uint32_t)tid / (kFlatCols / 4);
   constexpr uint32_t kRowStep = kFlatGridBlock / (kFlatCols / 4);
@@ -1097,7 +1098,9 @@ __global__ void __launch_bounds__(kFlatGridBlock) k_flatten_grid(int32_t* label,
   // usually a tile root): windows that reach that site later find the root
   // in one step.  Like the window's own stores this is a final value.
   {
-    int32_t cs[kFlatChase], cx[kFlatChase], c0[kFlatChase], c1[kFlatChase];
+    // per chase: its slot (-1: idle), the site it is at, the site it started
+    // from and that site's label once read
+    int32_t cs[kFlatChase], cx[kFlatChase], cfrom[kFlatChase], cnext[kFlatChase];
 #pragma unroll
     for (int c = 0; c < kFlatChase; ++c) cs[c] = -1;
     for (;;) {
@@ -1109,8 +1112,8 @@ __global__ void __launch_bounds__(kFlatGridBlock) k_flatten_grid(int32_t* label,
           pend &= pend - 1u;
           cs[c] = gslot(k >> 2) + (k & 3);
           cx[c] = lds_ld(w + cs[c]);
-          c0[c] = cx[c];  // where the chase starts
-          c1[c] = cx[c];  // its label, once read
+          cfrom[c] = cx[c];
+          cnext[c] = cx[c];
         }
         busy = busy || cs[c] >= 0;
       }
@@ -1122,8 +1125,8 @@ __global__ void __launch_bounds__(kFlatGridBlock) k_flatten_grid(int32_t* label,
       for (int c = 0; c < kFlatChase; ++c) {
         const bool root = cs[c] >= 0 && cy[c] == cx[c];
         if (root) lds_st(w + cs[c], cx[c] | kFinal);
-        if (root && c1[c] != cx[c]) label[c0[c]] = cx[c];
-        c1[c] = cs[c] >= 0 && c1[c] == c0[c] ? cy[c] : c1[c];
+        if (root && cnext[c] != cx[c]) label[cfrom[c]] = cx[c];  // more than one step
+        cnext[c] = cs[c] >= 0 && cnext[c] == cfrom[c] ? cy[c] : cnext[c];
         cx[c] = cs[c] >= 0 ? cy[c] : cx[c];
         cs[c] = root ? -1 : cs[c];
       }
